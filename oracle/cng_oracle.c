@@ -1,0 +1,616 @@
+/*
+ * CPU oracle for the alpha-CNG hot path (Li, Yan, Lu: "Fast-Convergent
+ * Proximity Graphs for Approximate Nearest Neighbor Search").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The GPU library shares
+ * no source, header or table with this file.
+ *
+ * Plain, slow, scalar code: every function follows the paper's definition or
+ * algorithm in the paper's order, with OpenMP only across independent rows or
+ * queries (results do not depend on the thread count).
+ *
+ * Two arithmetic modes:
+ *   ORC_FP64 (0): every distance and decision in double precision.
+ *   ORC_FP32 (1): the fixed-reduction-order single-precision arithmetic that the
+ *                 GPU path must reproduce bit for bit (see orc_dist_f32).
+ *
+ * Readings of points where the paper is silent (tie order, tau, centroid,
+ * connectivity edges) are stated at each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_NONE 0xFFFFFFFFu
+#define ORC_FP64 0
+#define ORC_FP32 1
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ECAPACITY = -5 };
+
+/* ------------------------------------------------------------------------- */
+/* Distances (paper Section 2.1: a metric; here Euclidean L2).  Ordering keys   */
+/* use the squared distance D; delta = sqrt(D) is used where the rule needs     */
+/* the metric itself (the additive tau term of Eq. (1)).                        */
+/* ------------------------------------------------------------------------- */
+
+/* Fixed-order single-precision squared distance.
+ * Element i belongs to lane l = (i/4) mod 32 and round r = i/128.  Each lane
+ * accumulates its elements in increasing i with a fused multiply-add
+ * (acc = fma(t, t, acc), t = x_i - y_i, acc starting at +0).  The 32 lane sums
+ * are then combined by a butterfly: for off = 16, 8, 4, 2, 1 every lane l
+ * replaces its value with value[l] + value[l ^ off]; the result is lane 0. */
+float orc_dist_f32(const float *x, const float *y, int d)
+{
+    float acc[32];
+    for (int l = 0; l < 32; ++l) acc[l] = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        int l = (i / 4) % 32;
+        float t = x[i] - y[i];
+        acc[l] = fmaf(t, t, acc[l]);
+    }
+    for (int off = 16; off >= 1; off /= 2) {
+        float next[32];
+        for (int l = 0; l < 32; ++l) next[l] = acc[l] + acc[l ^ off];
+        for (int l = 0; l < 32; ++l) acc[l] = next[l];
+    }
+    return acc[0];
+}
+
+/* The same order in double precision (inputs widened exactly). */
+double orc_dist_f64(const float *x, const float *y, int d)
+{
+    double acc[32];
+    for (int l = 0; l < 32; ++l) acc[l] = 0.0;
+    for (int i = 0; i < d; ++i) {
+        int l = (i / 4) % 32;
+        double t = (double)x[i] - (double)y[i];
+        acc[l] = fma(t, t, acc[l]);
+    }
+    for (int off = 16; off >= 1; off /= 2) {
+        double next[32];
+        for (int l = 0; l < 32; ++l) next[l] = acc[l] + acc[l ^ off];
+        for (int l = 0; l < 32; ++l) acc[l] = next[l];
+    }
+    return acc[0];
+}
+
+static double dist_mode(const float *x, const float *y, int d, int mode)
+{
+    return mode == ORC_FP32 ? (double)orc_dist_f32(x, y, d) : orc_dist_f64(x, y, d);
+}
+
+/* delta from D: correctly rounded square root in the mode's precision. */
+static double delta_mode(double D, int mode)
+{
+    return mode == ORC_FP32 ? (double)sqrtf((float)D) : sqrt(D);
+}
+
+/* Strict total order on (D, id): ties in distance go to the smaller id.  The
+ * paper gives no tie rule (Alg. 1 argmin, Alg. 2 sort); this pins one. */
+static int key_less(double Da, uint32_t ia, double Db, uint32_t ib)
+{
+    return Da < Db || (Da == Db && ia < ib);
+}
+
+typedef struct { double D; uint32_t id; } orc_key;
+
+static int cmp_key(const void *a, const void *b)
+{
+    const orc_key *x = (const orc_key *)a, *y = (const orc_key *)b;
+    if (key_less(x->D, x->id, y->D, y->id)) return -1;
+    if (key_less(y->D, y->id, x->D, x->id)) return 1;
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Exact candidates: for each row the C nearest columns by (D, id).            */
+/* Stands in for the local-neighbour set V of Section 4.1 (Alg. 3 phases 1-2), */
+/* computed exactly.  With exclude_self, column r is skipped for row r (the    */
+/* point itself); exact duplicates of it at D = 0 are kept.                    */
+/* ------------------------------------------------------------------------- */
+int orc_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int d, int C,
+            int exclude_self, int mode, uint32_t *ids, double *Dout)
+{
+    if (nr < 0 || nc < 0 || d < 1 || C < 1) return ORC_EINVAL;
+    int fail = 0;
+#pragma omp parallel
+    {
+        orc_key *best = (orc_key *)malloc(sizeof(orc_key) * (size_t)(C + 1));
+        if (!best) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t r = 0; r < nr; ++r) {
+            if (!best) continue;
+            int cnt = 0;
+            const float *x = rows + (size_t)r * d;
+            for (int64_t c = 0; c < nc; ++c) {
+                if (exclude_self && c == r) continue;
+                double D = dist_mode(x, cols + (size_t)c * d, d, mode);
+                uint32_t id = (uint32_t)c;
+                if (cnt == C && !key_less(D, id, best[C - 1].D, best[C - 1].id)) continue;
+                /* insertion into the sorted list of the best C so far */
+                int pos = cnt < C ? cnt : C - 1;
+                while (pos > 0 && key_less(D, id, best[pos - 1].D, best[pos - 1].id)) {
+                    best[pos] = best[pos - 1];
+                    --pos;
+                }
+                best[pos].D = D;
+                best[pos].id = id;
+                if (cnt < C) ++cnt;
+            }
+            for (int j = 0; j < C; ++j) {
+                ids[(size_t)r * C + j] = j < cnt ? best[j].id : ORC_NONE;
+                Dout[(size_t)r * C + j] = j < cnt ? best[j].D : INFINITY;
+            }
+        }
+        free(best);
+    }
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Edge pruning rule (Definition 2, Eq. (1)): candidate u of point p is pruned */
+/* by an already selected out-neighbour v iff                                  */
+/*        delta(p,u) > alpha * delta(u,v) + (alpha + 1) * tau.                 */
+/* The inequality is strict, so an exact tie keeps u.                          */
+/* In FP32 mode the decision is taken in single precision unless the two sides */
+/* are within 1e-6 (relative to delta(p,u)); such near-ties are re-decided     */
+/* from double-precision distances.                                            */
+/* ------------------------------------------------------------------------- */
+static int orc_prunes(const float *pts, int d, uint32_t p, uint32_t u, uint32_t v,
+                      double Dpu, double alpha, double tau, int mode)
+{
+    const float *xp = pts + (size_t)p * d, *xu = pts + (size_t)u * d, *xv = pts + (size_t)v * d;
+    if (mode == ORC_FP64) {
+        double a = sqrt(Dpu);
+        double b = sqrt(orc_dist_f64(xu, xv, d));
+        double lhs_b = alpha * b;
+        double c = (alpha + 1.0) * tau;
+        return a > lhs_b + c;
+    }
+    float a = sqrtf((float)Dpu);
+    float b = sqrtf(orc_dist_f32(xu, xv, d));
+    float al = (float)alpha, ta = (float)tau;
+    float c = (al + 1.0f) * ta;
+    float ab = al * b;
+    float rhs = ab + c;
+    float diff = fabsf(a - rhs);
+    float band = 1e-6f * a;
+    if (diff <= band) {
+        double a64 = sqrt(orc_dist_f64(xp, xu, d));
+        double b64 = sqrt(orc_dist_f64(xu, xv, d));
+        double ab64 = alpha * b64;
+        double c64 = (alpha + 1.0) * tau;
+        return a64 > ab64 + c64;
+    }
+    return a > rhs;
+}
+
+/* Alg. 2 pruning(p, V, alpha) on the candidate list of every point, keeping at
+ * most R out-neighbours, written into rows of width W >= R (padded with
+ * ORC_NONE; slots beyond R are spare slots for connectivity edges).  Stopping once R are kept equals returning the R
+ * closest points of the full shortcut set (the decision for u only involves
+ * earlier kept points).  Candidate lists are re-sorted by (D, id) first
+ * (Alg. 2 line 1); entries equal to ORC_NONE end a list. */
+int orc_prune(const float *pts, int64_t n, int d, const uint32_t *cand, const double *candD,
+              int C, int R, int W, double alpha, double tau, int mode, uint32_t *adj)
+{
+    if (n < 1 || d < 1 || C < 1 || R < 1 || W < R || !(alpha > 0.0) || !(tau >= 0.0))
+        return ORC_EINVAL;
+    int fail = 0;
+#pragma omp parallel
+    {
+        orc_key *V = (orc_key *)malloc(sizeof(orc_key) * (size_t)C);
+        uint32_t *S = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)R);
+        if (!V || !S) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < n; ++p) {
+            if (!V || !S) continue;
+            int nv = 0;
+            for (int j = 0; j < C; ++j) {
+                uint32_t u = cand[(size_t)p * C + j];
+                if (u == ORC_NONE) break;
+                V[nv].id = u;
+                V[nv].D = candD[(size_t)p * C + j];
+                ++nv;
+            }
+            qsort(V, (size_t)nv, sizeof(orc_key), cmp_key);
+            int ns = 0;
+            for (int j = 0; j < nv && ns < R; ++j) {
+                int pruned = 0;
+                for (int s = 0; s < ns && !pruned; ++s)
+                    pruned = orc_prunes(pts, d, (uint32_t)p, V[j].id, S[s], V[j].D, alpha, tau, mode);
+                if (!pruned) S[ns++] = V[j].id;
+            }
+            for (int s = 0; s < W; ++s) adj[(size_t)p * W + s] = s < ns ? S[s] : ORC_NONE;
+        }
+        free(V);
+        free(S);
+    }
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Entry point.  Alg. 3 uses the point found nearest to the centroid of P      */
+/* (the mean of all points).  Here it is found exactly: the centroid is the    */
+/* double-precision mean, summed sequentially inside blocks of 4096 points and */
+/* then sequentially over the block sums; the entry is the point minimising    */
+/* (squared distance in double, summed sequentially over dimensions, id).      */
+/* ------------------------------------------------------------------------- */
+uint32_t orc_medoid(const float *pts, int64_t n, int d)
+{
+    const int64_t B = 4096;
+    double *tot = (double *)calloc((size_t)d, sizeof(double));
+    double *blk = (double *)calloc((size_t)d, sizeof(double));
+    if (!tot || !blk || n < 1) { free(tot); free(blk); return ORC_NONE; }
+    for (int64_t a = 0; a < n; a += B) {
+        int64_t b = a + B < n ? a + B : n;
+        for (int i = 0; i < d; ++i) blk[i] = 0.0;
+        for (int64_t p = a; p < b; ++p)
+            for (int i = 0; i < d; ++i) blk[i] += (double)pts[(size_t)p * d + i];
+        for (int i = 0; i < d; ++i) tot[i] += blk[i];
+    }
+    for (int i = 0; i < d; ++i) tot[i] = tot[i] / (double)n;
+    double bestD = INFINITY;
+    uint32_t best = ORC_NONE;
+    for (int64_t p = 0; p < n; ++p) {
+        double acc = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double t = (double)pts[(size_t)p * d + i] - tot[i];
+            acc = fma(t, t, acc);
+        }
+        if (key_less(acc, (uint32_t)p, bestD, best)) { bestD = acc; best = (uint32_t)p; }
+    }
+    free(tot);
+    free(blk);
+    return best;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Beam search, Alg. 1 beam-search(G, q, s, L, k), taken literally:            */
+/*   Q <- {s}; E <- {}                                                         */
+/*   while Q \ E is not empty:                                                 */
+/*       u* <- the element of Q \ E with the smallest (D, id)                  */
+/*       Q <- Q united with every out-neighbour v of u*                        */
+/*       keep the L smallest of Q;  E <- E with u*                             */
+/*   return the k smallest of Q                                                */
+/* L is raised to k when k > L.  A row's out-neighbours are its entries before */
+/* the first ORC_NONE or out-of-range id.  hops = |E|; ndc counts the distinct */
+/* points whose distance to q was evaluated (the entry included).              */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double *D;
+    uint32_t *id;
+    unsigned char *expl;
+    unsigned char *seen; /* n bytes */
+    uint32_t *touched;   /* ids marked in seen (to clear) */
+    size_t ntouched, cap_touched;
+} orc_beam;
+
+static int beam_init(orc_beam *b, int64_t n, int cap)
+{
+    b->D = (double *)malloc(sizeof(double) * (size_t)cap);
+    b->id = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap);
+    b->expl = (unsigned char *)malloc((size_t)cap);
+    b->seen = (unsigned char *)calloc((size_t)n, 1);
+    b->cap_touched = 1024;
+    b->touched = (uint32_t *)malloc(sizeof(uint32_t) * b->cap_touched);
+    b->ntouched = 0;
+    return b->D && b->id && b->expl && b->seen && b->touched;
+}
+
+static void beam_free(orc_beam *b)
+{
+    free(b->D); free(b->id); free(b->expl); free(b->seen); free(b->touched);
+}
+
+static int beam_mark_seen(orc_beam *b, uint32_t v)
+{
+    if (b->seen[v]) return 0;
+    b->seen[v] = 1;
+    if (b->ntouched == b->cap_touched) {
+        size_t nc = b->cap_touched * 2;
+        uint32_t *t = (uint32_t *)realloc(b->touched, sizeof(uint32_t) * nc);
+        if (!t) return -1;
+        b->touched = t;
+        b->cap_touched = nc;
+    }
+    b->touched[b->ntouched++] = v;
+    return 1;
+}
+
+static void beam_clear_seen(orc_beam *b)
+{
+    for (size_t i = 0; i < b->ntouched; ++i) b->seen[b->touched[i]] = 0;
+    b->ntouched = 0;
+}
+
+/* One query.  Returns the final Q size (<= Leff); Q is left in b. */
+static int beam_one(orc_beam *b, const float *pts, int64_t n, int d, const uint32_t *adj, int R,
+                    const float *q, uint32_t s, int Leff, int mode, uint32_t *hops, uint32_t *ndc,
+                    uint32_t *trace, int trace_cap, int *trace_len)
+{
+    int qn = 1, h = 0;
+    uint32_t nd = 0;
+    b->D[0] = dist_mode(q, pts + (size_t)s * d, d, mode);
+    b->id[0] = s;
+    b->expl[0] = 0;
+    if (beam_mark_seen(b, s) > 0) ++nd;
+    for (;;) {
+        int i = 0;
+        while (i < qn && b->expl[i]) ++i; /* Q is kept sorted: first unexplored */
+        if (i == qn) break;
+        uint32_t u = b->id[i];
+        if (trace && h < trace_cap) trace[h] = u;
+        ++h;
+        for (int j = 0; j < R; ++j) {
+            uint32_t v = adj[(size_t)u * R + j];
+            if (v == ORC_NONE || (int64_t)v >= n) break;
+            int inq = 0;
+            for (int t = 0; t < qn; ++t)
+                if (b->id[t] == v) { inq = 1; break; }
+            if (inq) continue; /* set union */
+            double Dv = dist_mode(q, pts + (size_t)v * d, d, mode);
+            if (beam_mark_seen(b, v) > 0) ++nd;
+            int pos = qn;
+            while (pos > 0 && key_less(Dv, v, b->D[pos - 1], b->id[pos - 1])) {
+                b->D[pos] = b->D[pos - 1];
+                b->id[pos] = b->id[pos - 1];
+                b->expl[pos] = b->expl[pos - 1];
+                --pos;
+            }
+            b->D[pos] = Dv;
+            b->id[pos] = v;
+            b->expl[pos] = 0;
+            ++qn;
+        }
+        if (qn > Leff) qn = Leff; /* keep the L closest */
+        /* mark u* explored (it may have been cut by the truncation) */
+        for (int t = 0; t < qn; ++t)
+            if (b->id[t] == u) { b->expl[t] = 1; break; }
+    }
+    beam_clear_seen(b);
+    if (hops) *hops = (uint32_t)h;
+    if (ndc) *ndc = nd;
+    if (trace_len) *trace_len = h;
+    return qn;
+}
+
+int orc_search(const float *pts, int64_t n, int d, const uint32_t *adj, int R,
+               const float *queries, int64_t nq, int k, int L,
+               const uint32_t *entries, int64_t n_entries, int mode,
+               uint32_t *ids, double *dists, uint32_t *hops, uint32_t *ndc)
+{
+    if (n < 1 || d < 1 || R < 1 || k < 1 || L < 1 || nq < 0) return ORC_EINVAL;
+    if (n_entries != 1 && n_entries != nq) return ORC_EINVAL;
+    for (int64_t e = 0; e < n_entries; ++e)
+        if ((int64_t)entries[e] >= n) return ORC_EINVAL;
+    int Leff = L > k ? L : k;
+    int cap = Leff + R + 1;
+    int fail = 0;
+#pragma omp parallel
+    {
+        orc_beam b;
+        int ok = beam_init(&b, n, cap);
+        if (!ok) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < nq; ++i) {
+            if (!ok) continue;
+            uint32_t s = entries[n_entries == 1 ? 0 : i];
+            uint32_t h = 0, nd = 0;
+            int qn = beam_one(&b, pts, n, d, adj, R, queries + (size_t)i * d, s, Leff, mode, &h,
+                              &nd, NULL, 0, NULL);
+            for (int j = 0; j < k; ++j) {
+                ids[(size_t)i * k + j] = j < qn ? b.id[j] : ORC_NONE;
+                dists[(size_t)i * k + j] = j < qn ? delta_mode(b.D[j], mode) : INFINITY;
+            }
+            if (hops) hops[i] = h;
+            if (ndc) ndc[i] = nd;
+        }
+        beam_free(&b);
+    }
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* Single query with the sequence of hop vertices u* (Lemma 5 checks). */
+int orc_search_trace(const float *pts, int64_t n, int d, const uint32_t *adj, int R,
+                     const float *q, int k, int L, uint32_t entry, int mode,
+                     uint32_t *ids, double *dists, uint32_t *trace, int trace_cap, int *trace_len)
+{
+    if (n < 1 || d < 1 || R < 1 || k < 1 || L < 1 || (int64_t)entry >= n) return ORC_EINVAL;
+    int Leff = L > k ? L : k;
+    orc_beam b;
+    if (!beam_init(&b, n, Leff + R + 1)) { beam_free(&b); return ORC_ENOMEM; }
+    int qn = beam_one(&b, pts, n, d, adj, R, q, entry, Leff, mode, NULL, NULL, trace, trace_cap,
+                      trace_len);
+    for (int j = 0; j < k; ++j) {
+        ids[j] = j < qn ? b.id[j] : ORC_NONE;
+        dists[j] = j < qn ? delta_mode(b.D[j], mode) : INFINITY;
+    }
+    beam_free(&b);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Connectivity (Alg. 3 phase 4).  The paper only says that edges are added   */
+/* from the traversal tree of s so that every point is reachable.  Reading,    */
+/* in rounds on a fixed snapshot of the graph:                                 */
+/*   Reach <- points reachable from s.  If Reach = P: done.                    */
+/*   U <- P \ Reach.  A <- points of U with no in-edge from U (in id order);   */
+/*   if A is empty, A <- {min U}.                                              */
+/*   For every p in A: run beam-search(G, x_p, s, Lc, Lc) on the snapshot and */
+/*   let t_p be the first point of its result (by (D, id)) whose row has a     */
+/*   free slot; if none has one, the reached point with a free slot nearest to */
+/*   x_p by (D, id); if no reached point has a free slot: capacity error.      */
+/*   Then, in increasing p, append p to row t_p if that row still has a free   */
+/*   slot (a p that finds it full waits for the next round).                   */
+/* Rows have width W here (pruned edges plus spare slots); a row's out-degree  */
+/* is the number of entries before its first ORC_NONE.  The paper's phase 4   */
+/* follows NSG, whose tree growth adds edges regardless of the degree cap;     */
+/* the spare slots give those edges room without touching pruned edges.        */
+/* ------------------------------------------------------------------------- */
+static int row_degree(const uint32_t *adj, int R, uint32_t t)
+{
+    int g = 0;
+    while (g < R && adj[(size_t)t * R + g] != ORC_NONE) ++g;
+    return g;
+}
+
+static void bfs_mark(const uint32_t *adj, int64_t n, int R, unsigned char *reached, uint32_t *stack,
+                     uint32_t src)
+{
+    if (reached[src]) return;
+    int64_t top = 0;
+    reached[src] = 1;
+    stack[top++] = src;
+    while (top > 0) {
+        uint32_t u = stack[--top];
+        for (int j = 0; j < R; ++j) {
+            uint32_t v = adj[(size_t)u * R + j];
+            if (v == ORC_NONE || (int64_t)v >= n) break;
+            if (!reached[v]) { reached[v] = 1; stack[top++] = v; }
+        }
+    }
+}
+
+int orc_connect(const float *pts, int64_t n, int d, uint32_t *adj, int R, uint32_t entry, int Lc,
+                int mode, int64_t *n_added, int64_t *n_rounds)
+{
+    if (n < 1 || d < 1 || R < 1 || Lc < 1 || (int64_t)entry >= n) return ORC_EINVAL;
+    unsigned char *reached = (unsigned char *)calloc((size_t)n, 1);
+    uint32_t *stack = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *indeg = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *A = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *T = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    int *deg = (int *)malloc(sizeof(int) * (size_t)n);
+    int rc = ORC_OK;
+    int64_t added = 0, rounds = 0;
+    if (!reached || !stack || !indeg || !A || !T || !deg) { rc = ORC_ENOMEM; goto done; }
+    bfs_mark(adj, n, R, reached, stack, entry);
+    for (;;) {
+        int64_t nA = 0, minU = -1;
+        for (int64_t p = 0; p < n; ++p) indeg[p] = 0;
+        for (int64_t w = 0; w < n; ++w) {
+            if (reached[w]) continue;
+            if (minU < 0) minU = w;
+            for (int j = 0; j < R; ++j) {
+                uint32_t v = adj[(size_t)w * R + j];
+                if (v == ORC_NONE || (int64_t)v >= n) break;
+                if (!reached[v]) indeg[v]++;
+            }
+        }
+        if (minU < 0) break; /* everything reachable */
+        ++rounds;
+        for (int64_t p = 0; p < n; ++p)
+            if (!reached[p] && indeg[p] == 0) A[nA++] = (uint32_t)p;
+        if (nA == 0) A[nA++] = (uint32_t)minU;
+        for (int64_t t = 0; t < n; ++t) deg[t] = row_degree(adj, R, (uint32_t)t);
+        int fail = 0;
+#pragma omp parallel
+        {
+            orc_beam b;
+            int ok = beam_init(&b, n, Lc + R + 1);
+            if (!ok) {
+#pragma omp atomic write
+                fail = ORC_ENOMEM;
+            }
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t a = 0; a < nA; ++a) {
+                if (!ok) continue;
+                uint32_t p = A[a];
+                const float *xp = pts + (size_t)p * d;
+                int qn = beam_one(&b, pts, n, d, adj, R, xp, entry, Lc, mode, NULL, NULL, NULL, 0,
+                                  NULL);
+                uint32_t t = ORC_NONE;
+                for (int j = 0; j < qn; ++j)
+                    if (deg[b.id[j]] < R) { t = b.id[j]; break; }
+                if (t == ORC_NONE) { /* nearest reached point with room */
+                    double bD = INFINITY;
+                    for (int64_t w = 0; w < n; ++w) {
+                        if (!reached[w] || deg[w] >= R) continue;
+                        double D = dist_mode(xp, pts + (size_t)w * d, d, mode);
+                        if (key_less(D, (uint32_t)w, bD, t)) { bD = D; t = (uint32_t)w; }
+                    }
+                }
+                T[a] = t;
+            }
+            beam_free(&b);
+        }
+        if (fail) { rc = fail; goto done; }
+        for (int64_t a = 0; a < nA; ++a) {
+            uint32_t p = A[a], t = T[a];
+            if (t == ORC_NONE) { rc = ORC_ECAPACITY; goto done; }
+            if (deg[t] >= R) continue; /* taken earlier in this round: retry */
+            adj[(size_t)t * R + deg[t]] = p;
+            deg[t]++;
+            ++added;
+        }
+        /* reach(s) grows by what the new edges expose */
+        memset(reached, 0, (size_t)n);
+        bfs_mark(adj, n, R, reached, stack, entry);
+    }
+done:
+    if (n_added) *n_added = added;
+    if (n_rounds) *n_rounds = rounds;
+    free(reached); free(stack); free(indeg); free(A); free(T); free(deg);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole build with a fixed alpha: entry point, exact candidates, pruning of    */
+/* each candidate list (Alg. 2 with cap R), then connectivity.  Rows have      */
+/* width R + extra; the extra slots only ever hold connectivity edges.          */
+/* ------------------------------------------------------------------------- */
+int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, double alpha, double tau,
+              int mode, int connect, int Lc, uint32_t *adj, uint32_t *entry, int64_t *n_added)
+{
+    if (n < 2 || d < 1 || R < 1 || extra < 0 || C < 1) return ORC_EINVAL;
+    int W = R + extra;
+    int Ce = (int64_t)C > n - 1 ? (int)(n - 1) : C;
+    uint32_t *cand = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * Ce);
+    double *cD = (double *)malloc(sizeof(double) * (size_t)n * Ce);
+    int rc = ORC_OK;
+    if (!cand || !cD) { rc = ORC_ENOMEM; goto out; }
+    *entry = orc_medoid(pts, n, d);
+    rc = orc_knn(pts, n, pts, n, d, Ce, 1, mode, cand, cD);
+    if (rc) goto out;
+    rc = orc_prune(pts, n, d, cand, cD, Ce, R, W, alpha, tau, mode, adj);
+    if (rc) goto out;
+    if (n_added) *n_added = 0;
+    if (connect) rc = orc_connect(pts, n, d, adj, W, *entry, Lc > 0 ? Lc : Ce, mode, n_added, NULL);
+out:
+    free(cand);
+    free(cD);
+    return rc;
+}
