@@ -1,0 +1,175 @@
+/*
+ * cng.h -- C ABI of the MI355X (gfx950) alpha-CNG library (libcng.so).
+ *
+ * The library builds an alpha-convergent neighbourhood graph with a fixed alpha
+ * and searches it, following Li, Yan, Lu, "Fast-Convergent Proximity Graphs
+ * for Approximate Nearest Neighbor Search":
+ *   - edge pruning rule: Definition 2, Eq. (1); pruning procedure: Algorithm 2;
+ *   - construction framework: Algorithm 3 (entry point, candidate lists,
+ *     pruning, connectivity), with exact candidate lists in place of the
+ *     approximate K-NN graph and a fixed alpha (the paper's Fixed-alpha-CNG);
+ *   - beam search: Algorithm 1.
+ *
+ * Conventions (all entry points):
+ *   - Array pointers are DEVICE pointers unless the name ends in _host.  The
+ *     caller owns every buffer; the library never allocates device memory.
+ *     Scratch memory is passed in as `workspace` (size from *_workspace_size).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *     enqueue work and return, except where a function says it synchronises.
+ *   - Vectors are row-major float32, n rows of d contiguous values.
+ *   - Distances: Euclidean.  Ordering uses the squared distance D computed in
+ *     a fixed order (element i goes to lane (i/4) mod 32, lanes accumulate with
+ *     fused multiply-adds in increasing i, then a 16-8-4-2-1 butterfly); ties
+ *     in D are broken by the smaller id.  Returned distances are sqrt(D).
+ *   - An adjacency is n rows of W uint32 ids.  A row's out-neighbours are the
+ *     entries before its first CNG_NONE (or first id >= n); the rest is padding.
+ *   - Arguments are validated before any launch.  On a non-OK status nothing
+ *     was launched (EINVAL/EUNSUPPORTED) or outputs are undefined (EDEVICE);
+ *     cng_last_error() gives a message.  No C++ exception crosses the ABI.
+ *   - Not thread-safe on one stream; distinct streams are independent.
+ */
+#ifndef CNG_H
+#define CNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CNG_OK = 0,
+    CNG_EINVAL = -1,       /* an argument is out of range or inconsistent */
+    CNG_ENOMEM = -2,       /* workspace too small */
+    CNG_EDEVICE = -3,      /* a HIP call failed */
+    CNG_EUNSUPPORTED = -4, /* valid but outside what the kernels implement (e.g. L > 512) */
+    CNG_ECAPACITY = -5     /* connectivity could not attach a point: no row has a free slot */
+} cng_status;
+
+#define CNG_NONE 0xFFFFFFFFu
+
+/* Build flags */
+#define CNG_BUILD_CONNECT 1u /* run the connectivity phase (Algorithm 3, phase 4) */
+
+typedef struct {
+    int32_t R;           /* out-degree cap of pruning (Algorithm 2 keeps at most R), >= 1 */
+    int32_t extra;       /* spare slots per row for connectivity edges; row width W = R + extra */
+    int32_t C;           /* candidate-list size (the local-neighbour set V), clamped to n - 1 */
+    double alpha;        /* alpha of Eq. (1), > 0 */
+    double tau;          /* tau of Eq. (1), >= 0 */
+    uint32_t flags;      /* CNG_BUILD_* */
+    int32_t Lc;          /* beam width of the connectivity searches (0 = C) */
+    int32_t band;        /* per-row capacity of the candidate filter (0 = automatic) */
+    int32_t visited_log2;/* log2 of the search visited-table slots (0 = automatic) */
+} cng_build_params;
+
+typedef struct {
+    double ms_entry, ms_candidates, ms_prune, ms_connect, ms_total; /* stage wall times */
+    int64_t connect_rounds;    /* rounds of the connectivity phase */
+    int64_t connect_added;     /* edges added by the connectivity phase */
+    int64_t overflow_rows;     /* candidate rows recomputed exhaustively (filter band full) */
+    int32_t exact_integer;     /* 1 if the filter ran in exact small-integer mode */
+    int32_t filter_dtype;      /* 0 = fp32 MFMA filter, 1 = bf16 MFMA filter */
+} cng_build_stats;
+
+/* ------------------------------------------------------------------ build */
+
+/* Bytes of device workspace cng_build needs for n points of dimension d. */
+cng_status cng_build_workspace_size(int64_t n, int32_t d, const cng_build_params *p,
+                                    size_t *bytes_host);
+
+/* Build the graph (Algorithm 3 with exact candidates and fixed alpha).
+ *   points  [n x d] float32;  2 <= n < 2^31 - 1, 1 <= d <= 4096.
+ *   adj     [n x (R + extra)] uint32 output, CNG_NONE padded.  Columns 0..R-1
+ *           hold the pruned out-neighbours in increasing (D, id); further
+ *           columns only receive connectivity edges.
+ *   entry   [1] uint32 output: the point nearest the centroid (search entry).
+ *   stats_host  optional (NULL allowed).
+ * Synchronises `stream` (the connectivity phase is iterative) and returns
+ * when adj and entry are final. */
+cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_params *p,
+                     uint32_t *adj, uint32_t *entry, void *workspace, size_t workspace_bytes,
+                     void *stream, cng_build_stats *stats_host);
+
+/* Stage: entry point (Algorithm 3, phase 1: the point nearest to the centroid
+ * of P).  The centroid is the float64 mean (sequential sums inside blocks of
+ * 4096 points, then over the block sums); the entry minimises the float64
+ * squared distance to it (sequential over dimensions), ties to the smaller id.
+ * workspace >= cng_entry_workspace_size(n, d). */
+size_t cng_entry_workspace_size(int64_t n, int32_t d);
+cng_status cng_entry_point(const float *points, int64_t n, int32_t d, uint32_t *entry,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* Stage: exact candidate lists.  For every row r of `rows` [nr x d], the C
+ * columns of `cols` [nc x d] nearest by (D, id), ascending; with exclude_self
+ * (requires rows == cols, nr == nc) column r is skipped for row r.  Missing
+ * entries (C > available columns) are CNG_NONE / +inf.
+ *   ids [nr x C] uint32, D [nr x C] float32 squared distances (fixed order).
+ * Replaces the approximate K-NN graph + beam-search candidates of Algorithm 3
+ * (phases 1-2) by the exact C nearest neighbours. */
+cng_status cng_knn_workspace_size(int64_t nr, int64_t nc, int32_t d, int32_t C, int32_t band,
+                                  size_t *bytes_host);
+cng_status cng_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int32_t d,
+                   int32_t C, int32_t exclude_self, int32_t band, uint32_t *ids, float *D,
+                   void *workspace, size_t workspace_bytes, void *stream,
+                   int64_t *overflow_rows_host);
+
+/* Stage: pruning (Algorithm 2 with Eq. (1), fixed alpha, at most R kept).
+ *   cand [n x C] candidate ids of every point, ascending by (D, id), CNG_NONE
+ *        terminated; candD [n x C] their squared distances as returned by
+ *        cng_knn.  adj [n x W] output, W >= R.
+ * A candidate u is dropped iff an already kept v satisfies
+ *   sqrt(D(p,u)) > alpha * sqrt(D(u,v)) + (alpha + 1) * tau   (strict),
+ * evaluated in float32; when the two sides differ by at most 1e-6 relative the
+ * comparison is re-decided from float64 distances. */
+cng_status cng_prune(const float *points, int64_t n, int32_t d, const uint32_t *cand,
+                     const float *candD, int32_t C, int32_t R, int32_t W, double alpha,
+                     double tau, uint32_t *adj, void *stream);
+
+/* Stage: connectivity (Algorithm 3, phase 4) in place on adj [n x W].
+ * Rounds on a snapshot of the graph: let U be the points unreachable from
+ * `entry`; A = points of U without an in-edge from U (or the smallest id of U
+ * if none); each p in A is searched from `entry` with beam Lc and attached to
+ * the first result (by (D, id)) whose row has a free slot (else the nearest
+ * reachable point with a free slot); attachments are applied in increasing p,
+ * a p whose target filled up earlier in the round waits for the next round.
+ * Synchronises `stream`.  CNG_ECAPACITY if no reachable row has room. */
+cng_status cng_connect_workspace_size(int64_t n, int32_t W, int32_t Lc, size_t *bytes_host);
+cng_status cng_connect(const float *points, int64_t n, int32_t d, uint32_t *adj, int32_t W,
+                       uint32_t entry, int32_t Lc, int32_t visited_log2, void *workspace,
+                       size_t workspace_bytes, void *stream, int64_t *rounds_host,
+                       int64_t *added_host);
+
+/* ------------------------------------------------------------------ search */
+
+/* Batched beam search (Algorithm 1), one wavefront per query.
+ *   points [n x d], adj [n x W], queries [nq x d].
+ *   entries [n_entries]: n_entries == 1 (shared) or nq (one per query).
+ *   k >= 1; L >= 1; the beam keeps L_eff = max(L, k) <= 512 entries.
+ *   ids [nq x k] uint32, dists [nq x k] float32 (sqrt of D): the first k of
+ *   the final beam; CNG_NONE / +inf when fewer points were reached.
+ *   hops [nq], ndc [nq]: optional (NULL allowed): explored points and
+ *   distance evaluations per query.
+ *   visited_log2: log2 of the per-query visited-table slots in LDS, 6..14
+ *   (0 = automatic).  The table may forget old entries when full; results do
+ *   not depend on it, only ndc does.
+ * Requires W <= 256 and d <= 4096. */
+cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t *adj, int32_t W,
+                      const float *queries, int64_t nq, int32_t k, int32_t L,
+                      const uint32_t *entries, int64_t n_entries, uint32_t *ids, float *dists,
+                      uint32_t *hops, uint32_t *ndc, int32_t visited_log2, void *stream);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Message of the last non-OK status on the calling thread ("" if none). */
+const char *cng_last_error(void);
+
+/* Library version string. */
+const char *cng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CNG_H */

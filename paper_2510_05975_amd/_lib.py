@@ -1,0 +1,243 @@
+"""ctypes binding of libcng.so (the gfx950 alpha-CNG library).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step runs in the library's kernels.  uint32 ids travel in
+torch.int32 tensors (same bits; CNG_NONE reads as -1).
+
+The library must have been built (``paper_2510_05975_amd.build_lib.build()``);
+importing works without it, but every call raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcng.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cng.h")
+
+NONE = 0xFFFFFFFF
+BUILD_CONNECT = 1
+STATUS = {0: "CNG_OK", -1: "CNG_EINVAL", -2: "CNG_ENOMEM", -3: "CNG_EDEVICE",
+          -4: "CNG_EUNSUPPORTED", -5: "CNG_ECAPACITY"}
+
+
+class CngError(RuntimeError):
+    def __init__(self, func: str, status: int, msg: str):
+        super().__init__(f"{func}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BuildParams(C.Structure):
+    _fields_ = [("R", C.c_int32), ("extra", C.c_int32), ("C", C.c_int32), ("alpha", C.c_double),
+                ("tau", C.c_double), ("flags", C.c_uint32), ("Lc", C.c_int32), ("band", C.c_int32),
+                ("visited_log2", C.c_int32)]
+
+
+class BuildStats(C.Structure):
+    _fields_ = [("ms_entry", C.c_double), ("ms_candidates", C.c_double), ("ms_prune", C.c_double),
+                ("ms_connect", C.c_double), ("ms_total", C.c_double),
+                ("connect_rounds", C.c_int64), ("connect_added", C.c_int64),
+                ("overflow_rows", C.c_int64), ("exact_integer", C.c_int32),
+                ("filter_dtype", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+vp, i64, i32, u32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_size_t
+
+_SIGS = {
+    "cng_last_error": (C.c_char_p, []),
+    "cng_version": (C.c_char_p, []),
+    "cng_build_workspace_size": (C.c_int, [i64, i32, C.POINTER(BuildParams), C.POINTER(sz)]),
+    "cng_build": (C.c_int, [vp, i64, i32, C.POINTER(BuildParams), vp, vp, vp, sz, vp,
+                            C.POINTER(BuildStats)]),
+    "cng_entry_workspace_size": (sz, [i64, i32]),
+    "cng_entry_point": (C.c_int, [vp, i64, i32, vp, vp, sz, vp]),
+    "cng_knn_workspace_size": (C.c_int, [i64, i64, i32, i32, i32, C.POINTER(sz)]),
+    "cng_knn": (C.c_int, [vp, i64, vp, i64, i32, i32, i32, i32, vp, vp, vp, sz, vp,
+                          C.POINTER(i64)]),
+    "cng_prune": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]),
+    "cng_connect_workspace_size": (C.c_int, [i64, i32, i32, C.POINTER(sz)]),
+    "cng_connect": (C.c_int, [vp, i64, i32, vp, i32, u32, i32, i32, vp, sz, vp, C.POINTER(i64),
+                              C.POINTER(i64)]),
+    "cng_search": (C.c_int, [vp, i64, i32, vp, i32, vp, i64, i32, i32, vp, i64, vp, vp, vp, vp,
+                             i32, vp]),
+}
+
+
+def lib():
+    """Load libcng.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2510_05975_amd.build_lib")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/cng.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(cng_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _check(func: str, st: int):
+    if st != 0:
+        msg = lib().cng_last_error().decode()
+        raise CngError(func, st, msg)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _f32(x: torch.Tensor) -> torch.Tensor:
+    if x.dtype != torch.float32 or x.dim() != 2:
+        raise ValueError("expected a 2-D float32 tensor")
+    return x.contiguous()
+
+
+def _ids(x: torch.Tensor) -> torch.Tensor:
+    if x.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("expected int32 ids")
+    return x.contiguous()
+
+
+def version() -> str:
+    return lib().cng_version().decode()
+
+
+@dataclass
+class Graph:
+    adj: torch.Tensor      # [n, W] int32 (uint32 bits)
+    entry: int
+    R: int
+    stats: dict
+
+
+def build(points: torch.Tensor, R: int, C_: int, alpha: float, tau: float = 0.0, extra: int = 1,
+          connect: bool = True, Lc: int = 0, band: int = 0, visited_log2: int = 0) -> Graph:
+    """cng_build: entry point, exact candidates, pruning, connectivity."""
+    x = _f32(points)
+    n, d = x.shape
+    p = BuildParams(R, extra, C_, alpha, tau, BUILD_CONNECT if connect else 0, Lc, band, visited_log2)
+    nb = sz(0)
+    _check("cng_build_workspace_size", lib().cng_build_workspace_size(n, d, C.byref(p), C.byref(nb)))
+    ws = _ws(nb.value, x.device)
+    adj = torch.empty((n, R + extra), dtype=torch.int32, device=x.device)
+    entry = torch.empty(1, dtype=torch.int32, device=x.device)
+    st = BuildStats()
+    _check("cng_build", lib().cng_build(_ptr(x), n, d, C.byref(p), _ptr(adj), _ptr(entry), _ptr(ws),
+                                        nb.value, _stream(), C.byref(st)))
+    return Graph(adj, int(entry.item()) & 0xFFFFFFFF, R, st.as_dict())
+
+
+def entry_point(points: torch.Tensor) -> int:
+    x = _f32(points)
+    n, d = x.shape
+    nb = lib().cng_entry_workspace_size(n, d)
+    ws = _ws(nb, x.device)
+    out = torch.empty(1, dtype=torch.int32, device=x.device)
+    _check("cng_entry_point", lib().cng_entry_point(_ptr(x), n, d, _ptr(out), _ptr(ws), nb, _stream()))
+    return int(out.item()) & 0xFFFFFFFF
+
+
+def knn(rows: torch.Tensor, cols: torch.Tensor, C_: int, exclude_self: bool = False, band: int = 0):
+    """cng_knn -> (ids int32 [nr, C], D float32 [nr, C], overflow_rows)."""
+    r, c = _f32(rows), _f32(cols)
+    nr, d = r.shape
+    nc = c.shape[0]
+    nb = sz(0)
+    _check("cng_knn_workspace_size", lib().cng_knn_workspace_size(nr, nc, d, C_, band, C.byref(nb)))
+    ws = _ws(nb.value, r.device)
+    ids = torch.empty((nr, C_), dtype=torch.int32, device=r.device)
+    D = torch.empty((nr, C_), dtype=torch.float32, device=r.device)
+    ovf = i64(0)
+    same = exclude_self and rows.data_ptr() == cols.data_ptr()
+    rp = _ptr(r)
+    cp = rp if same else _ptr(c)
+    _check("cng_knn", lib().cng_knn(rp, nr, cp, nc, d, C_, int(exclude_self), band, _ptr(ids),
+                                    _ptr(D), _ptr(ws), nb.value, _stream(), C.byref(ovf)))
+    return ids, D, ovf.value
+
+
+def prune(points: torch.Tensor, cand: torch.Tensor, candD: torch.Tensor, R: int, alpha: float,
+          tau: float = 0.0, width: int | None = None) -> torch.Tensor:
+    x = _f32(points)
+    n, d = x.shape
+    cand, candD = _ids(cand), candD.contiguous()
+    W = R if width is None else width
+    adj = torch.empty((n, W), dtype=torch.int32, device=x.device)
+    _check("cng_prune", lib().cng_prune(_ptr(x), n, d, _ptr(cand), _ptr(candD), cand.shape[1], R, W,
+                                        alpha, tau, _ptr(adj), _stream()))
+    return adj
+
+
+def connect(points: torch.Tensor, adj: torch.Tensor, entry: int, Lc: int, visited_log2: int = 0):
+    """cng_connect in place on adj -> (rounds, added)."""
+    x = _f32(points)
+    n, d = x.shape
+    adj = _ids(adj)
+    W = adj.shape[1]
+    nb = sz(0)
+    _check("cng_connect_workspace_size", lib().cng_connect_workspace_size(n, W, Lc, C.byref(nb)))
+    ws = _ws(nb.value, x.device)
+    rounds, added = i64(0), i64(0)
+    _check("cng_connect", lib().cng_connect(_ptr(x), n, d, _ptr(adj), W, entry, Lc, visited_log2,
+                                            _ptr(ws), nb.value, _stream(), C.byref(rounds),
+                                            C.byref(added)))
+    return rounds.value, added.value
+
+
+def search(points: torch.Tensor, adj: torch.Tensor, queries: torch.Tensor, k: int, L: int,
+           entries, visited_log2: int = 0, stats: bool = False, out=None):
+    """cng_search -> (ids int32 [nq, k], dists float32 [nq, k], hops, ndc)."""
+    x, q = _f32(points), _f32(queries)
+    n, d = x.shape
+    nq = q.shape[0]
+    adj = _ids(adj)
+    if isinstance(entries, int):
+        entries = torch.tensor([entries & 0xFFFFFFFF], dtype=torch.int64).to(torch.int32).to(x.device)
+    entries = _ids(entries)
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=x.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=x.device)
+        hops = torch.empty(nq, dtype=torch.int32, device=x.device) if stats else None
+        ndc = torch.empty(nq, dtype=torch.int32, device=x.device) if stats else None
+    else:
+        ids, dists, hops, ndc = out
+    _check("cng_search", lib().cng_search(_ptr(x), n, d, _ptr(adj), adj.shape[1], _ptr(q), nq, k, L,
+                                          _ptr(entries), entries.numel(), _ptr(ids), _ptr(dists),
+                                          _ptr(hops), _ptr(ndc), visited_log2, _stream()))
+    return ids, dists, hops, ndc
+
+
+def u32(t: torch.Tensor):
+    """Device int32 ids -> host numpy uint32."""
+    return t.cpu().numpy().view("uint32")

@@ -1,0 +1,335 @@
+// C ABI of libcng: argument validation, workspace layout and the build
+// pipeline (Algorithm 3 with exact candidates and fixed alpha):
+//   entry point -> exact candidate lists -> pruning (Algorithm 2, Eq. (1))
+//   -> connectivity (phase 4).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+
+#include "../../include/cng.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+cng_status fail(cng_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+cng_status fail(cng_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+cng_status ok()
+{
+    g_err.clear();
+    return CNG_OK;
+}
+
+cng_status hip_fail(hipError_t e, const char *where)
+{
+    return fail(CNG_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+constexpr int64_t MAX_N = 2147483646;  // ids are uint32 with bit 31 never set
+constexpr int MAX_W = 256;
+constexpr int MAX_LEFF = 512;
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+cng_status check_points(const void *p, int64_t n, int32_t d, int64_t nmin)
+{
+    if (n < nmin || n > MAX_N) return fail(CNG_EINVAL, "n=%lld out of range [%lld, %lld]", (long long)n, (long long)nmin, (long long)MAX_N);
+    if (d < 1 || d > 4096) return fail(CNG_EINVAL, "d=%d out of range [1, 4096]", d);
+    if (!p) return fail(CNG_EINVAL, "points is NULL");
+    return CNG_OK;
+}
+
+struct BuildSizes {
+    int Ceff, W, Lc;
+    cng::KnnPlan knn;
+    size_t cand_ids, cand_D, entry, connect, total;
+};
+
+cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSizes *z)
+{
+    cng_status s = check_points((const void *)1, n, d, 2);
+    if (s != CNG_OK) return s;
+    if (!p) return fail(CNG_EINVAL, "params is NULL");
+    if (p->R < 1) return fail(CNG_EINVAL, "R=%d must be >= 1", p->R);
+    if (p->extra < 0) return fail(CNG_EINVAL, "extra=%d must be >= 0", p->extra);
+    if (p->R + p->extra > MAX_W) return fail(CNG_EUNSUPPORTED, "row width R+extra=%d exceeds %d", p->R + p->extra, MAX_W);
+    if (p->C < 1) return fail(CNG_EINVAL, "C=%d must be >= 1", p->C);
+    if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(CNG_EINVAL, "alpha must be finite and > 0");
+    if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(CNG_EINVAL, "tau must be finite and >= 0");
+    if (p->Lc < 0) return fail(CNG_EINVAL, "Lc=%d must be >= 0", p->Lc);
+    if (p->band < 0 || p->band > 512) return fail(CNG_EUNSUPPORTED, "band=%d must be in [0, 512]", p->band);
+    if (p->visited_log2 != 0 && (p->visited_log2 < 6 || p->visited_log2 > 14))
+        return fail(CNG_EINVAL, "visited_log2=%d must be 0 or in [6, 14]", p->visited_log2);
+    z->Ceff = (int64_t)p->C > n - 1 ? (int)(n - 1) : p->C;
+    if (2 * z->Ceff + 128 > 512 && p->band == 0) {
+        if (z->Ceff > 192) return fail(CNG_EUNSUPPORTED, "C=%d exceeds 192", p->C);
+    }
+    z->W = p->R + p->extra;
+    z->Lc = p->Lc > 0 ? p->Lc : z->Ceff;
+    if (z->Lc > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "Lc=%d exceeds %d", z->Lc, MAX_LEFF);
+    z->knn = cng::knn_plan(n, n, d, z->Ceff, p->band);
+    z->cand_ids = align256((size_t)n * z->Ceff * 4);
+    z->cand_D = align256((size_t)n * z->Ceff * 4);
+    z->entry = align256(cng::entry_workspace_bytes(n, d));
+    z->connect = align256(cng::connect_workspace_bytes(n, z->W, z->Lc));
+    size_t scratch = z->entry;
+    if (z->knn.bytes > scratch) scratch = z->knn.bytes;
+    if (z->connect > scratch) scratch = z->connect;
+    z->total = z->cand_ids + z->cand_D + align256(scratch);
+    return CNG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cng_last_error(void) { return g_err.c_str(); }
+
+const char *cng_version(void) { return "cng-gfx950 0.1"; }
+
+cng_status cng_build_workspace_size(int64_t n, int32_t d, const cng_build_params *p, size_t *bytes)
+{
+    if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
+    BuildSizes z;
+    cng_status s = build_sizes(n, d, p, &z);
+    if (s != CNG_OK) return s;
+    *bytes = z.total;
+    return ok();
+}
+
+cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_params *p,
+                     uint32_t *adj, uint32_t *entry, void *workspace, size_t ws_bytes, void *stream,
+                     cng_build_stats *stats)
+{
+    BuildSizes z;
+    cng_status s = check_points(points, n, d, 2);
+    if (s != CNG_OK) return s;
+    s = build_sizes(n, d, p, &z);
+    if (s != CNG_OK) return s;
+    if (!adj || !entry) return fail(CNG_EINVAL, "adj/entry is NULL");
+    if (!workspace || ws_bytes < z.total)
+        return fail(CNG_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, z.total);
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)workspace;
+    uint32_t *cand = (uint32_t *)w;
+    float *candD = (float *)(w + z.cand_ids);
+    void *scratch = w + z.cand_ids + z.cand_D;
+    cng_build_stats local{};
+    cng_build_stats *S = stats ? stats : &local;
+    std::memset(S, 0, sizeof *S);
+    hipError_t e;
+    const double t0 = now_ms();
+
+    e = cng::launch_entry(points, n, d, entry, scratch, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "entry point");
+    uint32_t entry_h = 0;
+    e = hipMemcpyAsync(&entry_h, entry, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "entry point");
+    const double t1 = now_ms();
+
+    int64_t ovf = 0;
+    int exact = 0, dtype = 0;
+    e = cng::launch_knn(points, n, points, n, d, z.Ceff, 1, z.knn, cand, candD, scratch, st, &ovf,
+                        &exact, &dtype);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "candidates");
+    const double t2 = now_ms();
+
+    e = cng::launch_prune(points, n, d, cand, candD, z.Ceff, p->R, z.W, p->alpha, p->tau, adj, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "prune");
+    const double t3 = now_ms();
+
+    int64_t rounds = 0, added = 0;
+    if (p->flags & CNG_BUILD_CONNECT) {
+        int cap = 0;
+        const int vl = p->visited_log2 ? p->visited_log2 : cng::search_default_vlog2(z.Lc);
+        e = cng::run_connect(points, n, d, adj, z.W, entry_h, z.Lc, vl, scratch, st, &rounds, &added, &cap);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "connect");
+        if (cap) return fail(CNG_ECAPACITY, "connectivity: no reachable row has a free slot");
+    }
+    const double t4 = now_ms();
+    S->ms_entry = t1 - t0;
+    S->ms_candidates = t2 - t1;
+    S->ms_prune = t3 - t2;
+    S->ms_connect = t4 - t3;
+    S->ms_total = t4 - t0;
+    S->connect_rounds = rounds;
+    S->connect_added = added;
+    S->overflow_rows = ovf;
+    S->exact_integer = exact;
+    S->filter_dtype = dtype;
+    return ok();
+}
+
+size_t cng_entry_workspace_size(int64_t n, int32_t d)
+{
+    if (n < 1 || d < 1) return 0;
+    return cng::entry_workspace_bytes(n, d);
+}
+
+cng_status cng_entry_point(const float *points, int64_t n, int32_t d, uint32_t *entry,
+                           void *workspace, size_t ws_bytes, void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (!entry) return fail(CNG_EINVAL, "entry is NULL");
+    if (!workspace || ws_bytes < cng::entry_workspace_bytes(n, d))
+        return fail(CNG_ENOMEM, "workspace too small");
+    hipError_t e = cng::launch_entry(points, n, d, entry, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "entry point");
+    return ok();
+}
+
+cng_status cng_knn_workspace_size(int64_t nr, int64_t nc, int32_t d, int32_t C, int32_t band,
+                                  size_t *bytes)
+{
+    if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
+    if (nr < 0 || nr > MAX_N || nc < 1 || nc > MAX_N) return fail(CNG_EINVAL, "nr/nc out of range");
+    if (d < 1 || d > 4096) return fail(CNG_EINVAL, "d out of range");
+    if (C < 1) return fail(CNG_EINVAL, "C must be >= 1");
+    if (band < 0 || band > 512) return fail(CNG_EUNSUPPORTED, "band must be in [0, 512]");
+    int Ce = C;
+    if (band == 0 && 2 * Ce + 128 > 512) return fail(CNG_EUNSUPPORTED, "C=%d exceeds 192", C);
+    *bytes = cng::knn_plan(nr, nc, d, Ce, band).bytes;
+    return ok();
+}
+
+cng_status cng_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int32_t d, int32_t C,
+                   int32_t exclude_self, int32_t band, uint32_t *ids, float *D, void *workspace,
+                   size_t ws_bytes, void *stream, int64_t *overflow_rows_host)
+{
+    size_t need = 0;
+    cng_status s = cng_knn_workspace_size(nr, nc, d, C, band, &need);
+    if (s != CNG_OK) return s;
+    if (!rows || !cols || !ids || !D) return fail(CNG_EINVAL, "NULL array argument");
+    if (exclude_self && (rows != cols || nr != nc)) return fail(CNG_EINVAL, "exclude_self needs rows == cols");
+    if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    if (nr == 0) return ok();
+    cng::KnnPlan plan = cng::knn_plan(nr, nc, d, C, band);
+    int64_t ovf = 0;
+    int exact = 0, dtype = 0;
+    hipError_t e = cng::launch_knn(rows, nr, cols, nc, d, C, exclude_self ? 1 : 0, plan, ids, D,
+                                   workspace, (hipStream_t)stream, &ovf, &exact, &dtype);
+    if (e != hipSuccess) return hip_fail(e, "knn");
+    if (overflow_rows_host) *overflow_rows_host = ovf;
+    return ok();
+}
+
+cng_status cng_prune(const float *points, int64_t n, int32_t d, const uint32_t *cand,
+                     const float *candD, int32_t C, int32_t R, int32_t W, double alpha, double tau,
+                     uint32_t *adj, void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (!cand || !candD || !adj) return fail(CNG_EINVAL, "NULL array argument");
+    if (C < 1 || R < 1 || W < R) return fail(CNG_EINVAL, "need C >= 1, R >= 1, W >= R");
+    if (W > MAX_W) return fail(CNG_EUNSUPPORTED, "W=%d exceeds %d", W, MAX_W);
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(CNG_EINVAL, "alpha must be finite and > 0");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(CNG_EINVAL, "tau must be finite and >= 0");
+    hipError_t e = cng::launch_prune(points, n, d, cand, candD, C, R, W, alpha, tau, adj, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "prune");
+    return ok();
+}
+
+cng_status cng_connect_workspace_size(int64_t n, int32_t W, int32_t Lc, size_t *bytes)
+{
+    if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
+    if (n < 1 || n > MAX_N || W < 1 || W > MAX_W || Lc < 1 || Lc > MAX_LEFF)
+        return fail(CNG_EINVAL, "n/W/Lc out of range");
+    *bytes = cng::connect_workspace_bytes(n, W, Lc);
+    return ok();
+}
+
+cng_status cng_connect(const float *points, int64_t n, int32_t d, uint32_t *adj, int32_t W,
+                       uint32_t entry, int32_t Lc, int32_t visited_log2, void *workspace,
+                       size_t ws_bytes, void *stream, int64_t *rounds_host, int64_t *added_host)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    size_t need = 0;
+    s = cng_connect_workspace_size(n, W, Lc, &need);
+    if (s != CNG_OK) return s;
+    if (!adj) return fail(CNG_EINVAL, "adj is NULL");
+    if ((int64_t)entry >= n) return fail(CNG_EINVAL, "entry %u >= n", entry);
+    if (visited_log2 != 0 && (visited_log2 < 6 || visited_log2 > 14)) return fail(CNG_EINVAL, "visited_log2 out of range");
+    if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t rounds = 0, added = 0;
+    int cap = 0;
+    const int vl = visited_log2 ? visited_log2 : cng::search_default_vlog2(Lc);
+    hipError_t e = cng::run_connect(points, n, d, adj, W, entry, Lc, vl, workspace, st, &rounds, &added, &cap);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "connect");
+    if (rounds_host) *rounds_host = rounds;
+    if (added_host) *added_host = added;
+    if (cap) return fail(CNG_ECAPACITY, "connectivity: no reachable row has a free slot");
+    return ok();
+}
+
+cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t *adj, int32_t W,
+                      const float *queries, int64_t nq, int32_t k, int32_t L,
+                      const uint32_t *entries, int64_t n_entries, uint32_t *ids, float *dists,
+                      uint32_t *hops, uint32_t *ndc, int32_t visited_log2, void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (W < 1) return fail(CNG_EINVAL, "W=%d must be >= 1", W);
+    if (W > MAX_W) return fail(CNG_EUNSUPPORTED, "W=%d exceeds %d", W, MAX_W);
+    if (nq < 0 || nq > MAX_N) return fail(CNG_EINVAL, "nq out of range");
+    if (k < 1 || L < 1) return fail(CNG_EINVAL, "k and L must be >= 1");
+    const int Leff = L > k ? L : k;
+    if (Leff > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "max(L, k)=%d exceeds %d", Leff, MAX_LEFF);
+    if (n_entries != 1 && n_entries != nq) return fail(CNG_EINVAL, "n_entries must be 1 or nq");
+    if (visited_log2 != 0 && (visited_log2 < 6 || visited_log2 > 14)) return fail(CNG_EINVAL, "visited_log2 out of range");
+    if (nq == 0) return ok();
+    if (!adj || !queries || !entries || !ids || !dists) return fail(CNG_EINVAL, "NULL array argument");
+    cng::SearchArgs a{};
+    a.points = points;
+    a.n = n;
+    a.d = d;
+    a.adj = adj;
+    a.W = W;
+    a.queries = queries;
+    a.query_ids = nullptr;
+    a.nq = nq;
+    a.k = k;
+    a.Leff = Leff;
+    a.entries = entries;
+    a.per_query_entry = n_entries == nq && nq > 1 ? 1 : (n_entries == 1 ? 0 : 1);
+    a.ids = ids;
+    a.dists = dists;
+    a.hops = hops;
+    a.ndc = ndc;
+    a.vlog2 = visited_log2 ? visited_log2 : cng::search_default_vlog2(Leff);
+    hipError_t e = cng::launch_search(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "search");
+    return ok();
+}
+
+}  // extern "C"

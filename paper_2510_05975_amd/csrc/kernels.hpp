@@ -1,0 +1,59 @@
+// Internal launch interfaces of the gfx950 kernels (host side of libcng).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cng {
+
+struct SearchArgs {
+    const float *points;
+    int64_t n;
+    int d;
+    const uint32_t *adj;
+    int W;
+    const float *queries;      // [nq x d], or nullptr when query_ids is set
+    const uint32_t *query_ids; // optional: query i is points[query_ids[i]]
+    int64_t nq;
+    int k, Leff;
+    const uint32_t *entries;
+    int per_query_entry;
+    uint32_t *ids;
+    float *dists;
+    uint32_t *hops, *ndc;
+    int vlog2;
+};
+
+hipError_t launch_search(const SearchArgs &a, hipStream_t stream);
+int search_default_vlog2(int Leff);
+size_t search_lds_per_wave(int Leff, int vlog2);
+
+// entry point (centroid rule)
+size_t entry_workspace_bytes(int64_t n, int d);
+hipError_t launch_entry(const float *points, int64_t n, int d, uint32_t *entry, void *ws,
+                        hipStream_t stream);
+
+// exact candidates
+struct KnnPlan {
+    int64_t chunk_rows;   // rows per pass
+    int band;             // per-row band capacity
+    size_t bytes;         // workspace bytes
+};
+KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band);
+hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int d, int C,
+                      int exclude_self, const KnnPlan &plan, uint32_t *ids, float *D, void *ws,
+                      hipStream_t stream, int64_t *overflow_rows, int *exact_int, int *dtype);
+
+// pruning
+hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *cand,
+                        const float *candD, int C, int R, int W, double alpha, double tau,
+                        uint32_t *adj, hipStream_t stream);
+
+// connectivity
+size_t connect_workspace_bytes(int64_t n, int W, int Lc);
+hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int W,
+                       uint32_t entry_host, int Lc, int vlog2, void *ws, hipStream_t stream,
+                       int64_t *rounds, int64_t *added, int *capacity_error);
+
+}  // namespace cng

@@ -1,0 +1,637 @@
+// Exact candidate lists: for every row x the C columns y nearest by (D, id),
+// D in the fixed reduction order.  This stands in for the local-neighbour set
+// V of Algorithm 3 (phases 1-2), computed exactly.
+//
+// Stage 1, filter (MFMA): a workgroup owns 128 rows and sweeps all column
+// tiles of 128.  For each pair it computes F = |y|^2 - 2 x.y on the matrix
+// cores (float32 accumulate) and appends (F, id) to the row's band when F is at
+// most the row threshold.  Whenever a band could overflow on the next tile it
+// is compacted: sorted, and cut to F <= F_C + 2E where F_C is the C-th smallest
+// F so far and E bounds |F - (D - |x|^2)| for every column of this row (the
+// product and norm rounding of the filter plus the rounding of D itself).  Any
+// point of the exact top C then satisfies F <= F_C + 2E, so the band always
+// contains it.  With small-integer data every quantity is an exact integer and
+// E = 0.
+// Stage 2, rerank: D is recomputed for the band in the fixed order and the top
+// C by (D, id) is selected by a bitonic sort.
+// Stage 3: rows whose band overflowed are recomputed exhaustively.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cng {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128, BN = 128, BK = 32, APAD = 4;
+constexpr int NT = 256;  // threads of the filter workgroup
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ uint32_t fkey(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unfkey(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+
+// Smallest float >= v.
+__device__ __forceinline__ float float_up(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) {
+        uint32_t u = __float_as_uint(f);
+        if (f > 0.f) u += 1;
+        else if (f < 0.f) u -= 1;
+        else u = 1;  // +0 -> smallest subnormal
+        f = __uint_as_float(u);
+    }
+    return f;
+}
+
+// Bitonic sort of n (power of two) 64-bit keys in LDS by one wavefront.
+__device__ void wave_sort(uint64_t *k, int n)
+{
+    const int lane = lane_id();
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            wave_sync();
+            for (int t = lane; t < n / 2; t += 64) {
+                int i = 2 * t - (t & (stride - 1));
+                int j = i + stride;
+                bool up = (i & size) == 0;
+                uint64_t a = k[i], b = k[j];
+                if ((a > b) == up) {
+                    k[i] = b;
+                    k[j] = a;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// ---------------------------------------------------------------- prep
+struct PrepOut {
+    uint32_t max_norm_bits;  // max |y| over columns (float bits, >= 0)
+    uint32_t all_int;        // 1 while every value seen is an integer
+    uint32_t max_abs_bits;   // max |value| (float bits)
+    uint32_t any_neg;        // 1 if a value < 0
+    uint32_t overflow;       // rows recomputed exhaustively
+    uint32_t pad[3];
+};
+
+// Squared norms of columns (any order: part of the filter's error bound),
+// norms of rows, and the small-integer test.
+__global__ void prep_cols(const float *__restrict__ y, int64_t nc, int d, float *__restrict__ ny,
+                          PrepOut *st)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool isint = true, neg = false;
+    float mabs = 0.f, nrm = 0.f;
+    if (c < nc) {
+        const float *row = y + (size_t)c * d;
+        float s = 0.f;
+        for (int i = 0; i < d; ++i) {
+            float v = row[i];
+            s = __builtin_fmaf(v, v, s);
+            isint = isint && (v == __builtin_rintf(v));
+            neg = neg || v < 0.f;
+            mabs = __builtin_fmaxf(mabs, __builtin_fabsf(v));
+        }
+        ny[c] = s;
+        nrm = __builtin_sqrtf(s);
+    }
+    if (!isint) atomicAnd(&st->all_int, 0u);
+    if (neg) atomicOr(&st->any_neg, 1u);
+    atomicMax(&st->max_abs_bits, __float_as_uint(mabs));
+    atomicMax(&st->max_norm_bits, __float_as_uint(nrm));
+}
+
+__global__ void prep_rows(const float *__restrict__ x, int64_t nr, int d, float *__restrict__ xn,
+                          PrepOut *st)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool isint = true, neg = false;
+    float mabs = 0.f;
+    if (r < nr) {
+        const float *row = x + (size_t)r * d;
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) {
+            float v = row[i];
+            s += (double)v * (double)v;
+            isint = isint && (v == __builtin_rintf(v));
+            neg = neg || v < 0.f;
+            mabs = __builtin_fmaxf(mabs, __builtin_fabsf(v));
+        }
+        xn[r] = float_up(__builtin_sqrt(s) * (1.0 + 1e-12));
+    }
+    if (!isint) atomicAnd(&st->all_int, 0u);
+    if (neg) atomicOr(&st->any_neg, 1u);
+    atomicMax(&st->max_abs_bits, __float_as_uint(mabs));
+}
+
+// Per-row error bound E = kappa * (|x| + max|y|)^2 (0 in exact-integer mode).
+__global__ void row_bounds(const float *__restrict__ xn, int64_t nr, const PrepOut *st, double kappa,
+                           int exact, float *__restrict__ E)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    if (exact) {
+        E[r] = 0.f;
+        return;
+    }
+    double my = (double)__uint_as_float(st->max_norm_bits) * (1.0 + 1e-6);
+    double s = (double)xn[r] + my;
+    E[r] = float_up(kappa * s * s);
+}
+
+// ---------------------------------------------------------------- filter
+struct FilterArgs {
+    const float *rows;
+    int64_t nr, r0;  // rows r0 .. r0 + chunk handled by this launch
+    int64_t chunk;
+    const float *cols;
+    int64_t nc;
+    int d;
+    int C;
+    int exclude_self;
+    const float *ny;
+    const float *E;  // indexed by global row
+    int CB;
+    float *bandF;    // [chunk x CB]
+    uint32_t *bandI;
+    int *cnt;        // [chunk]; -1 = overflowed
+    PrepOut *st;
+};
+
+struct FilterLds {
+    float *As, *Bs, *thr, *erow;
+    int *cnt;
+    uint64_t *sort;  // 4 x CB
+};
+
+// Compact the band of local row li (one wave); updates thr/cnt.  After the
+// last tile a band may stay large (no further appends follow).
+__device__ void compact_row(const FilterArgs &a, FilterLds &s, int li, uint64_t *buf, bool last)
+{
+    const int lane = lane_id();
+    const int64_t lr = (int64_t)blockIdx.x * BM + li;  // row within the chunk
+    float *bF = a.bandF + (size_t)lr * a.CB;
+    uint32_t *bI = a.bandI + (size_t)lr * a.CB;
+    int c = s.cnt[li];
+    if (c > a.CB) c = a.CB;
+    int np = 1;
+    while (np < c) np <<= 1;
+    for (int e = lane; e < np; e += 64)
+        buf[e] = e < c ? (((uint64_t)fkey(bF[e]) << 32) | bI[e]) : ~0ull;
+    wave_sort(buf, np);
+    int keep = c;
+    float thr = s.thr[li];
+    if (c >= a.C) {
+        float fc = unfkey((uint32_t)(buf[a.C - 1] >> 32));
+        thr = float_up((double)fc + 2.0 * (double)s.erow[li]);
+        uint32_t tk = fkey(thr);
+        // entries are sorted: count those with F <= thr
+        int cntk = 0;
+        for (int e0 = 0; e0 < c; e0 += 64) {
+            int e = e0 + lane;
+            bool in = e < c && (uint32_t)(buf[e] >> 32) <= tk;
+            cntk += __popcll(ballot(in));
+        }
+        keep = cntk;
+    }
+    for (int e = lane; e < keep; e += 64) {
+        bF[e] = unfkey((uint32_t)(buf[e] >> 32));
+        bI[e] = (uint32_t)buf[e];
+    }
+    wave_sync();
+    if (lane == 0) {
+        if (!last && keep > a.CB - BN) {  // cannot take another tile: recompute exhaustively
+            s.cnt[li] = -1;
+            s.thr[li] = -__builtin_inff();
+        } else {
+            s.cnt[li] = keep;
+            s.thr[li] = thr;
+        }
+    }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void load_tile(const float *__restrict__ src, int64_t nrows, int64_t row0,
+                                          int d, int k0, float *__restrict__ dst)
+{
+    // BM x BK floats, stored k-major: dst[k * (BM + APAD) + row]
+    for (int f = threadIdx.x; f < BM * BK / 4; f += NT) {
+        int row = f / (BK / 4), kq = f % (BK / 4);
+        int64_t gr = row0 + row;
+        int k = k0 + kq * 4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gr < nrows) {
+            const float *p = src + (size_t)gr * d + k;
+            if (VEC) {
+                if (k < d) v = *reinterpret_cast<const float4 *>(p);
+            } else {
+                v.x = k + 0 < d ? p[0] : 0.f;
+                v.y = k + 1 < d ? p[1] : 0.f;
+                v.z = k + 2 < d ? p[2] : 0.f;
+                v.w = k + 3 < d ? p[3] : 0.f;
+            }
+        }
+        dst[(kq * 4 + 0) * (BM + APAD) + row] = v.x;
+        dst[(kq * 4 + 1) * (BM + APAD) + row] = v.y;
+        dst[(kq * 4 + 2) * (BM + APAD) + row] = v.z;
+        dst[(kq * 4 + 3) * (BM + APAD) + row] = v.w;
+    }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(NT) void filter_f32(FilterArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    FilterLds s;
+    s.As = reinterpret_cast<float *>(smem);
+    s.Bs = s.As + BK * (BM + APAD);
+    s.thr = s.Bs + BK * (BN + APAD);
+    s.erow = s.thr + BM;
+    s.cnt = reinterpret_cast<int *>(s.erow + BM);
+    s.sort = reinterpret_cast<uint64_t *>(s.cnt + BM + 2);  // +2 keeps 8-byte alignment slack
+    s.sort = reinterpret_cast<uint64_t *>(((uintptr_t)s.sort + 7) & ~(uintptr_t)7);
+
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int wr = wave >> 1, wc = wave & 1;
+    const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM;  // global first row
+    const int64_t rend = a.r0 + a.chunk < a.nr ? a.r0 + a.chunk : a.nr;
+
+    for (int li = threadIdx.x; li < BM; li += NT) {
+        int64_t gi = row0 + li;
+        bool live = gi < rend;
+        s.thr[li] = live ? __builtin_inff() : -__builtin_inff();
+        s.erow[li] = live ? a.E[gi] : 0.f;
+        s.cnt[li] = 0;
+    }
+    __syncthreads();
+
+    for (int64_t col0 = 0; col0 < a.nc; col0 += BN) {
+        floatx16 acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+        for (int k0 = 0; k0 < a.d; k0 += BK) {
+            load_tile<VEC>(a.rows, rend, row0, a.d, k0, s.As);
+            load_tile<VEC>(a.cols, a.nc, col0, a.d, k0, s.Bs);
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < BK; kk += 2) {
+                const int k = kk + (lane >> 5);
+                float af[2], bf[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) af[i] = s.As[k * (BM + APAD) + wr * 64 + i * 32 + (lane & 31)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) bf[j] = s.Bs[k * (BN + APAD) + wc * 64 + j * 32 + (lane & 31)];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+
+        // ---- epilogue: threshold test and append
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t gj = col0 + wc * 64 + j * 32 + (lane & 31);
+            if (gj >= a.nc) continue;
+            const float nyj = a.ny[gj];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int li = wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int64_t gi = row0 + li;
+                    if (gi >= rend || (a.exclude_self && gi == gj)) continue;
+                    const float F = nyj - 2.0f * acc[i][j][r];
+                    if (F <= s.thr[li]) {
+                        int pos = atomicAdd(&s.cnt[li], 1);
+                        if (pos < a.CB) {
+                            const size_t o = (size_t)(gi - a.r0) * a.CB + pos;
+                            a.bandF[o] = F;
+                            a.bandI[o] = (uint32_t)gj;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- compaction of rows that could overflow on the next tile
+        const bool last = col0 + BN >= a.nc;
+        for (int li = wave; li < BM; li += NT / 64) {
+            const int c = s.cnt[li];
+            const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN);
+            if (need) compact_row(a, s, li, s.sort + (size_t)wave * a.CB, last);
+        }
+        __syncthreads();
+    }
+    for (int li = threadIdx.x; li < BM; li += NT) {
+        int64_t gi = row0 + li;
+        if (gi < rend) {
+            a.cnt[gi - a.r0] = s.cnt[li];
+            if (s.cnt[li] < 0) atomicAdd(&a.st->overflow, 1u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- rerank
+struct RerankArgs {
+    const float *rows;
+    int64_t r0, chunk, nr;
+    const float *cols;
+    int64_t nc;
+    int d, C, CB;
+    const float *bandF;
+    const uint32_t *bandI;
+    const int *cnt;
+    uint32_t *ids;  // [nr x C]
+    float *D;
+};
+
+template <int G, int RND, bool VEC>
+__global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a)
+{
+    constexpr int NG = 64 / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int grp = lane / G, gl = lane % G;
+    const int64_t lr = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t gi = a.r0 + lr;
+    if (lr >= a.chunk || gi >= a.nr) return;
+    const int c = a.cnt[lr];
+    if (c < 0) return;  // exhaustive path
+    uint64_t *buf = reinterpret_cast<uint64_t *>(smem) + (size_t)wave * a.CB;
+    const float *x = a.rows + (size_t)gi * a.d;
+    float4 xr[RND];
+#pragma unroll
+    for (int r = 0; r < RND; ++r) xr[r] = load_chunk<VEC>(x, a.d, r, gl);
+    const uint32_t *bI = a.bandI + (size_t)lr * a.CB;
+    for (int b = 0; b < c; b += NG) {
+        const int e = b + grp;
+        float4 yr[RND];
+        uint32_t id = NONE;
+        if (e < c) {
+            id = bI[e];
+            const float *y = a.cols + (size_t)id * a.d;
+#pragma unroll
+            for (int r = 0; r < RND; ++r) yr[r] = load_chunk<VEC>(y, a.d, r, gl);
+        } else {
+#pragma unroll
+            for (int r = 0; r < RND; ++r) yr[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int r = 0; r < RND; ++r) acc = chunk_fma(xr[r], yr[r], acc);
+        acc = group_sum<G>(acc);
+        if (gl == 0 && e < c) buf[e] = make_key(acc, id);
+    }
+    int np = 1;
+    while (np < c) np <<= 1;
+    wave_sync();
+    for (int e = c + lane; e < np; e += 64) buf[e] = ~0ull;
+    wave_sync();
+    wave_sort(buf, np);
+    for (int e = lane; e < a.C; e += 64) {
+        uint32_t id = NONE;
+        float dd = __builtin_inff();
+        if (e < c) {
+            id = key_id(buf[e]);
+            dd = key_dist(buf[e]);
+        }
+        a.ids[(size_t)gi * a.C + e] = id;
+        a.D[(size_t)gi * a.C + e] = dd;
+    }
+}
+
+// ---------------------------------------------------------------- exhaustive
+// One wave per row whose band overflowed: every column, exact keys, an LDS
+// buffer of CB keys cut back to the best C whenever it fills.
+template <int G, int RND, bool VEC>
+__global__ __launch_bounds__(256) void exhaustive_kernel(RerankArgs a, int exclude_self, int CBX)
+{
+    constexpr int NG = 64 / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int grp = lane / G, gl = lane % G;
+    const int64_t lr = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t gi = a.r0 + lr;
+    if (lr >= a.chunk || gi >= a.nr) return;
+    if (a.cnt[lr] >= 0) return;
+    // CBX (a power of two) >= C + 64: room for one more batch after a cut to C
+    uint64_t *buf = reinterpret_cast<uint64_t *>(smem) + (size_t)wave * CBX;
+    const float *x = a.rows + (size_t)gi * a.d;
+    float4 xr[RND];
+#pragma unroll
+    for (int r = 0; r < RND; ++r) xr[r] = load_chunk<VEC>(x, a.d, r, gl);
+    int fill = 0;
+    uint64_t thr = ~0ull;
+    for (int64_t b = 0; b < a.nc; b += NG) {
+        const int64_t col = b + grp;
+        float4 yr[RND];
+        const bool in = col < a.nc && !(exclude_self && col == gi);
+        if (in) {
+            const float *y = a.cols + (size_t)col * a.d;
+#pragma unroll
+            for (int r = 0; r < RND; ++r) yr[r] = load_chunk<VEC>(y, a.d, r, gl);
+        } else {
+#pragma unroll
+            for (int r = 0; r < RND; ++r) yr[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int r = 0; r < RND; ++r) acc = chunk_fma(xr[r], yr[r], acc);
+        acc = group_sum<G>(acc);
+        const uint64_t key = make_key(acc, (uint32_t)col);
+        const bool take = in && gl == 0 && key < thr;
+        const uint64_t tm = ballot(take);
+        if (take) buf[fill + __popcll(tm & ((1ull << lane) - 1ull))] = key;
+        fill += __popcll(tm);
+        if (fill + NG > CBX) {  // full: keep the best C (fill > CBX - NG >= C here)
+            wave_sync();
+            for (int e = fill + lane; e < CBX; e += 64) buf[e] = ~0ull;
+            wave_sort(buf, CBX);
+            fill = a.C;
+            thr = buf[a.C - 1];
+        }
+    }
+    int np = 1;
+    while (np < fill) np <<= 1;
+    wave_sync();
+    for (int e = fill + lane; e < np; e += 64) buf[e] = ~0ull;
+    wave_sync();
+    wave_sort(buf, np);
+    for (int e = lane; e < a.C; e += 64) {
+        uint32_t id = NONE;
+        float dd = __builtin_inff();
+        if (e < fill) {
+            id = key_id(buf[e]);
+            dd = key_dist(buf[e]);
+        }
+        a.ids[(size_t)gi * a.C + e] = id;
+        a.D[(size_t)gi * a.C + e] = dd;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+namespace {
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+__global__ void init_prep(PrepOut *st)
+{
+    st->max_norm_bits = 0;
+    st->all_int = 1;
+    st->max_abs_bits = 0;
+    st->any_neg = 0;
+    st->overflow = 0;
+}
+
+using RerankFn = void (*)(RerankArgs);
+using ExhFn = void (*)(RerankArgs, int, int);
+
+template <int G, int RND, bool VEC>
+void pick_gr(RerankFn &r, ExhFn &e)
+{
+    r = rerank_kernel<G, RND, VEC>;
+    e = exhaustive_kernel<G, RND, VEC>;
+}
+
+template <bool VEC>
+void pick_rerank(int d, RerankFn &r, ExhFn &e)
+{
+    if (d <= 32) return pick_gr<8, 1, VEC>(r, e);
+    if (d <= 64) return pick_gr<16, 1, VEC>(r, e);
+    int rnd = (d + 127) / 128;
+    if (rnd <= 1) return pick_gr<32, 1, VEC>(r, e);
+    if (rnd <= 2) return pick_gr<32, 2, VEC>(r, e);
+    if (rnd <= 4) return pick_gr<32, 4, VEC>(r, e);
+    if (rnd <= 8) return pick_gr<32, 8, VEC>(r, e);
+    if (rnd <= 16) return pick_gr<32, 16, VEC>(r, e);
+    return pick_gr<32, 32, VEC>(r, e);
+}
+
+size_t filter_lds_bytes(int CB)
+{
+    size_t b = (size_t)BK * (BM + APAD) * 4 * 2 + (size_t)BM * 4 * 2 + (size_t)(BM + 2) * 4;
+    b = (b + 15) & ~(size_t)15;
+    return b + (size_t)(NT / 64) * CB * 8;
+}
+
+}  // namespace
+
+KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
+{
+    (void)d;
+    KnnPlan p;
+    int CB = band > 0 ? next_pow2(band) : next_pow2(2 * C + BN);
+    if (CB < 64) CB = 64;
+    p.band = CB;
+    const size_t budget = (size_t)1 << 30;  // band bytes per pass
+    int64_t chunk = (int64_t)(budget / ((size_t)CB * 8));
+    chunk = chunk / BM * BM;
+    if (chunk < BM) chunk = BM;
+    int64_t nr_pad = (nr + BM - 1) / BM * BM;
+    if (chunk > nr_pad) chunk = nr_pad;
+    p.chunk_rows = chunk;
+    p.bytes = align256((size_t)nc * 4) + align256((size_t)nr * 4) * 2 + align256(sizeof(PrepOut)) +
+              align256((size_t)chunk * CB * 4) * 2 + align256((size_t)chunk * 4);
+    return p;
+}
+
+hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int d, int C,
+                      int exclude_self, const KnnPlan &plan, uint32_t *ids, float *D, void *ws,
+                      hipStream_t stream, int64_t *overflow_rows, int *exact_int, int *dtype)
+{
+    unsigned char *w = (unsigned char *)ws;
+    float *ny = (float *)w;
+    w += align256((size_t)nc * 4);
+    float *xn = (float *)w;
+    w += align256((size_t)nr * 4);
+    float *E = (float *)w;
+    w += align256((size_t)nr * 4);
+    PrepOut *st = (PrepOut *)w;
+    w += align256(sizeof(PrepOut));
+    const int CB = plan.band;
+    float *bandF = (float *)w;
+    w += align256((size_t)plan.chunk_rows * CB * 4);
+    uint32_t *bandI = (uint32_t *)w;
+    w += align256((size_t)plan.chunk_rows * CB * 4);
+    int *cnt = (int *)w;
+
+    hipLaunchKernelGGL(init_prep, dim3(1), dim3(1), 0, stream, st);
+    hipLaunchKernelGGL(prep_cols, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream, cols, nc,
+                       d, ny, st);
+    hipLaunchKernelGGL(prep_rows, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, rows, nr,
+                       d, xn, st);
+    PrepOut h;
+    hipError_t e = hipMemcpyAsync(&h, st, sizeof(PrepOut), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    // exact small-integer mode: every partial sum of the filter and of D is an
+    // integer below 2^24, so both are exact and the band needs no margin
+    const double M = (double)__builtin_bit_cast(float, h.max_abs_bits);
+    const double lim = 16777216.0;
+    bool exact = h.all_int != 0 &&
+                 (h.any_neg ? 4.0 * d * M * M <= lim : 2.0 * d * M * M <= lim);
+    if (exact_int) *exact_int = exact ? 1 : 0;
+    if (dtype) *dtype = 0;
+    const double kappa = (6.0 * d + 40.0) * 5.9604644775390625e-8;  // (6d + 40) * 2^-24
+    hipLaunchKernelGGL(row_bounds, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, xn, nr,
+                       st, kappa, exact ? 1 : 0, E);
+
+    const bool vec = (d % 4 == 0) && ((uintptr_t)rows % 16 == 0) && ((uintptr_t)cols % 16 == 0);
+    RerankFn rfn;
+    ExhFn efn;
+    if (vec) pick_rerank<true>(d, rfn, efn);
+    else pick_rerank<false>(d, rfn, efn);
+    const size_t flds = filter_lds_bytes(CB);
+    for (int64_t r0 = 0; r0 < nr; r0 += plan.chunk_rows) {
+        const int64_t chunk = nr - r0 < plan.chunk_rows ? nr - r0 : plan.chunk_rows;
+        FilterArgs fa{rows, nr, r0, chunk, cols, nc, d, C, exclude_self, ny, E, CB, bandF, bandI, cnt, st};
+        const unsigned fblocks = (unsigned)((chunk + BM - 1) / BM);
+        if (vec) hipLaunchKernelGGL(filter_f32<true>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
+        else hipLaunchKernelGGL(filter_f32<false>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
+        RerankArgs ra{rows, r0, chunk, nr, cols, nc, d, C, CB, bandF, bandI, cnt, ids, D};
+        const unsigned rblocks = (unsigned)((chunk + 3) / 4);
+        hipLaunchKernelGGL(rfn, dim3(rblocks), dim3(256), (unsigned)(4 * CB * 8), stream, ra);
+        const int CBX = next_pow2(2 * C + 64 > CB ? 2 * C + 64 : CB);
+        hipLaunchKernelGGL(efn, dim3(rblocks), dim3(256), (unsigned)(4 * CBX * 8), stream, ra,
+                           exclude_self, CBX);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&h, st, sizeof(PrepOut), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(stream);
+    if (overflow_rows) *overflow_rows = h.overflow;
+    return e;
+}
+
+}  // namespace cng

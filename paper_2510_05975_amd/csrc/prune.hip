@@ -1,0 +1,166 @@
+// Edge pruning (Definition 2, Eq. (1)) with the pruning procedure of
+// Algorithm 2 applied to every point's candidate list, one wavefront per point.
+//
+// Candidates arrive ascending by (D, id) (Algorithm 2, line 1, done by the
+// candidate stage).  For candidate u the wave evaluates D(u, v) for every
+// already kept v, G lanes per pair, 64/G pairs per instruction, all loads of a
+// batch in flight together; u is dropped as soon as one pair satisfies
+//     sqrt(D(p,u)) > alpha * sqrt(D(u,v)) + (alpha + 1) * tau      (strict).
+// The comparison is made in float32.  When |lhs - rhs| <= 1e-6 * lhs the pair
+// is re-decided from float64 distances of the same reduction order.  At most R
+// candidates are kept (stopping there equals keeping the R closest of the full
+// shortcut set, since a decision only looks at earlier kept points).
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cng {
+
+namespace {
+
+struct PruneArgs {
+    const float *points;
+    int64_t n;
+    int d;
+    const uint32_t *cand;
+    const float *candD;
+    int C, R, W;
+    double alpha, tau;
+    uint32_t *adj;
+};
+
+template <int G, int RND, bool VEC>
+__device__ __forceinline__ double dist_f64_group(const float *__restrict__ x,
+                                                 const float *__restrict__ y, int d, int gl)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < RND; ++r)
+        acc = chunk_fma_f64(load_chunk<VEC>(x, d, r, gl), load_chunk<VEC>(y, d, r, gl), acc);
+    return group_sum_f64<G>(acc);
+}
+
+template <int G, int RND, bool VEC, int UB>
+__global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
+{
+    constexpr int NG = 64 / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int grp = lane / G, gl = lane % G;
+    const int64_t p = (int64_t)blockIdx.x * wpb + wave;
+    if (p >= a.n) return;
+    uint32_t *S = reinterpret_cast<uint32_t *>(smem) + (size_t)wave * a.R;
+    const int d = a.d;
+
+    const float al = (float)a.alpha, ta = (float)a.tau;
+    const float cterm = (al + 1.0f) * ta;
+    const float *xp = a.points + (size_t)p * d;
+
+    int ns = 0;
+    for (int j = 0; j < a.C && ns < a.R; ++j) {
+        const uint32_t u = a.cand[(size_t)p * a.C + j];
+        if (u == NONE || (int64_t)u >= a.n) break;
+        const float lhs = __builtin_sqrtf(a.candD[(size_t)p * a.C + j]);
+        const float *xu = a.points + (size_t)u * d;
+        float4 ur[RND];
+#pragma unroll
+        for (int r = 0; r < RND; ++r) ur[r] = load_chunk<VEC>(xu, d, r, gl);
+        bool pruned = false;
+        for (int b = 0; b < ns && !pruned; b += NG * UB) {
+            float4 vr[UB][RND];
+#pragma unroll
+            for (int t = 0; t < UB; ++t) {
+                int c = b + t * NG + grp;
+                if (c < ns) {
+                    const float *xv = a.points + (size_t)S[c] * d;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) vr[t][r] = load_chunk<VEC>(xv, d, r, gl);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) vr[t][r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            bool hit = false;
+#pragma unroll
+            for (int t = 0; t < UB; ++t) {
+                float acc = 0.f;
+#pragma unroll
+                for (int r = 0; r < RND; ++r) acc = chunk_fma(ur[r], vr[t][r], acc);
+                acc = group_sum<G>(acc);
+                const int c = b + t * NG + grp;
+                if (c < ns) {
+                    const float dist = __builtin_sqrtf(acc);
+                    const float ab = al * dist;
+                    const float rhs = ab + cterm;
+                    const float diff = __builtin_fabsf(lhs - rhs);
+                    const float band = 1e-6f * lhs;
+                    bool dec;
+                    if (diff <= band) {  // near-tie: re-decide in float64 (same for the whole group)
+                        const float *xv = a.points + (size_t)S[c] * d;
+                        double a64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xp, xu, d, gl));
+                        double b64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xu, xv, d, gl));
+                        double ab64 = a.alpha * b64;
+                        double c64 = (a.alpha + 1.0) * a.tau;
+                        dec = a64 > ab64 + c64;
+                    } else {
+                        dec = lhs > rhs;
+                    }
+                    hit = hit || (dec && gl == 0);
+                }
+            }
+            pruned = ballot(hit) != 0;
+        }
+        if (!pruned) {
+            wave_sync();
+            if (lane == 0) S[ns] = u;
+            wave_sync();
+            ++ns;
+        }
+    }
+    uint32_t *out = a.adj + (size_t)p * a.W;
+    for (int s = lane; s < a.W; s += 64) out[s] = s < ns ? S[s] : NONE;
+}
+
+using PruneFn = void (*)(PruneArgs);
+
+template <int G, int RND, bool VEC>
+PruneFn prune_fn()
+{
+    constexpr int UB = G == 32 ? (RND >= 8 ? 1 : 8 / RND) : 4;
+    return prune_kernel<G, RND, VEC, UB>;
+}
+
+template <bool VEC>
+PruneFn pick_prune(int d)
+{
+    if (d <= 32) return prune_fn<8, 1, VEC>();
+    if (d <= 64) return prune_fn<16, 1, VEC>();
+    int rnd = (d + 127) / 128;
+    if (rnd <= 1) return prune_fn<32, 1, VEC>();
+    if (rnd <= 2) return prune_fn<32, 2, VEC>();
+    if (rnd <= 4) return prune_fn<32, 4, VEC>();
+    if (rnd <= 8) return prune_fn<32, 8, VEC>();
+    if (rnd <= 16) return prune_fn<32, 16, VEC>();
+    return prune_fn<32, 32, VEC>();
+}
+
+}  // namespace
+
+hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *cand,
+                        const float *candD, int C, int R, int W, double alpha, double tau,
+                        uint32_t *adj, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj};
+    const bool vec = (d % 4 == 0) && ((uintptr_t)points % 16 == 0);
+    PruneFn fn = vec ? pick_prune<true>(d) : pick_prune<false>(d);
+    const int wpb = 4;
+    const int64_t blocks = (n + wpb - 1) / wpb;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), (unsigned)(wpb * R * 4), stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace cng

@@ -1,0 +1,328 @@
+// Batched beam search over a proximity graph: Algorithm 1 of the paper
+// (beam-search(G, q, s, L, k), Section 2.2), one wavefront per query.
+//
+// Per wavefront, in LDS:
+//   beam   two ping-pong arrays of L_eff keys (D, id), ascending; bit 63 of a
+//          key marks the point as explored (the set E of Algorithm 1);
+//   vis    an open-addressing table of ids whose distance was computed.  It
+//          never reports an id it has not seen, so skipping those ids leaves
+//          the beam identical to Algorithm 1 at every step (a point that left
+//          or never entered the beam cannot re-enter: the beam's L-th key only
+//          decreases).  When a probe sequence is full an old id is overwritten;
+//          that costs a repeated distance evaluation, never a different result.
+// Per hop: the row of the first unexplored point is read with one coalesced
+// load, unseen neighbours are compacted, their vectors are gathered with one
+// dwordx4 per lane per 128 dimensions (G lanes per vector, 64/G vectors per
+// instruction, all loads of a batch in flight together) and reduced with a
+// lane butterfly in the fixed order, then merged into the beam by rank.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cng {
+
+namespace {
+
+constexpr int PROBES = 8;
+
+__device__ __forceinline__ bool visit(uint32_t *vis, int vlog2, uint32_t id)
+{
+    const uint32_t mask = (1u << vlog2) - 1u;
+    const uint32_t h = (id * 0x9E3779B1u) >> (32 - vlog2);
+    for (int t = 0; t < PROBES; ++t) {
+        uint32_t slot = (h + (uint32_t)t) & mask;
+        uint32_t cur = vis[slot];
+        if (cur == id) return false;
+        if (cur == NONE) {
+            uint32_t old = atomicCAS(&vis[slot], NONE, id);
+            if (old == NONE) return true;
+            if (old == id) return false;
+        }
+    }
+    // every probed slot holds another id: forget the one at h
+    return atomicExch(&vis[h], id) != id;
+}
+
+// First index e < qn of the beam whose key is not explored, or -1.
+template <int QS>
+__device__ __forceinline__ int first_unexplored(const uint64_t *beam, int qn)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < QS; ++j) {
+        int e = j * 64 + lane;
+        bool un = e < qn && !(beam[e] & EXPL);
+        uint64_t m = ballot(un);
+        if (m) return j * 64 + (__ffsll((unsigned long long)m) - 1);
+        if ((j + 1) * 64 >= qn) break;
+    }
+    return -1;
+}
+
+// Number of entries of sorted arr[0..cnt) that are < key.
+__device__ __forceinline__ int lower_bound_keys(const uint64_t *arr, int cnt, uint64_t key)
+{
+    int lo = 0, hi = cnt;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (key_mask(arr[mid]) < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct WaveLds {
+    uint64_t *qa, *qb, *tmp;
+    float *dsc;
+    uint32_t *cid, *vis;
+};
+
+__host__ __device__ constexpr size_t wave_lds_bytes(int qcap, int vlog2)
+{
+    return (size_t)2 * qcap * 8 + 64 * 8 + 64 * 4 + 64 * 4 + ((size_t)4 << vlog2);
+}
+
+// One query.  G lanes per vector, RND float4 rounds per lane, QS beam slots per lane.
+template <int G, int RND, bool VEC, int QS, int UB>
+__device__ void beam_query(const SearchArgs &a, int64_t qi, WaveLds s)
+{
+    constexpr int NG = 64 / G;
+    const int lane = lane_id();
+    const int grp = lane / G, gl = lane % G;
+    const int d = a.d;
+    const int Leff = a.Leff;
+
+    const float *qv = a.query_ids ? a.points + (size_t)a.query_ids[qi] * d : a.queries + (size_t)qi * d;
+    float4 qr[RND];
+#pragma unroll
+    for (int r = 0; r < RND; ++r) qr[r] = load_chunk<VEC>(qv, d, r, gl);
+
+    for (int i = lane; i < (1 << a.vlog2); i += 64) s.vis[i] = NONE;
+    wave_sync();
+
+    const uint32_t s0 = a.entries[a.per_query_entry ? qi : 0];
+    if ((int64_t)s0 >= a.n) {  // invalid entry: nothing is reachable
+        for (int e = lane; e < a.k; e += 64) {
+            a.ids[(size_t)qi * a.k + e] = NONE;
+            a.dists[(size_t)qi * a.k + e] = __builtin_inff();
+        }
+        if (lane == 0) {
+            if (a.hops) a.hops[qi] = 0;
+            if (a.ndc) a.ndc[qi] = 0;
+        }
+        return;
+    }
+    {
+        const float *row = a.points + (size_t)s0 * d;
+        float acc = 0.f;
+#pragma unroll
+        for (int r = 0; r < RND; ++r) acc = chunk_fma(load_chunk<VEC>(row, d, r, gl), qr[r], acc);
+        acc = group_sum<G>(acc);
+        if (lane == 0) {
+            s.qa[0] = make_key(acc, s0);
+            visit(s.vis, a.vlog2, s0);
+        }
+    }
+    wave_sync();
+    int qn = 1;
+    uint32_t hops = 0, ndc = 1;
+    uint64_t *qa = s.qa, *qb = s.qb;
+
+    for (;;) {
+        const int f = first_unexplored<QS>(qa, qn);
+        if (f < 0) break;
+        const uint32_t u = key_id(qa[f]);
+        wave_sync();
+        if (lane == 0) qa[f] |= EXPL;
+        ++hops;
+        const uint32_t *row = a.adj + (size_t)u * a.W;
+        for (int c0 = 0; c0 < a.W; c0 += 64) {
+            // ---- neighbours of u*: coalesced row load, cut at the first sentinel
+            uint32_t v = c0 + lane < a.W ? row[c0 + lane] : NONE;
+            bool ok = v != NONE && (int64_t)v < a.n;
+            uint64_t bad = ballot(!ok);
+            int cut = bad ? (__ffsll((unsigned long long)bad) - 1) : 64;
+            ok = ok && lane < cut;
+            // ---- visited filter + compaction
+            bool fresh = ok && visit(s.vis, a.vlog2, v);
+            uint64_t fm = ballot(fresh);
+            int m = __popcll(fm);
+            if (fresh) {
+                int slot = __popcll(fm & ((1ull << lane) - 1ull));
+                s.cid[slot] = v;
+            }
+            wave_sync();
+            // ---- distances: G lanes per vector, NG vectors per instruction
+            for (int b = 0; b < m; b += NG * UB) {
+                float4 xv[UB][RND];
+#pragma unroll
+                for (int t = 0; t < UB; ++t) {
+                    int c = b + t * NG + grp;
+                    if (c < m) {
+                        const float *xr = a.points + (size_t)s.cid[c] * d;
+#pragma unroll
+                        for (int r = 0; r < RND; ++r) xv[t][r] = load_chunk<VEC>(xr, d, r, gl);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < RND; ++r) xv[t][r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < UB; ++t) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) acc = chunk_fma(xv[t][r], qr[r], acc);
+                    acc = group_sum<G>(acc);
+                    int c = b + t * NG + grp;
+                    if (gl == 0 && c < m) s.dsc[c] = acc;
+                }
+            }
+            wave_sync();
+            ndc += (uint32_t)m;
+            // ---- merge the m new keys into the beam (Algorithm 1: union, keep the L closest)
+            bool val = lane < m;
+            uint64_t kc = val ? make_key(s.dsc[lane], s.cid[lane]) : KEY_INF;
+            if (qn == Leff) val = val && kc < key_mask(qa[Leff - 1]);
+            int lb = 0;
+            if (val) {
+                lb = lower_bound_keys(qa, qn, kc);
+                // an id the visited table forgot may still be in the beam: same key, drop it
+                if (lb < qn && key_mask(qa[lb]) == kc) val = false;
+            }
+            uint64_t sm = ballot(val);
+            int ns = __popcll(sm);
+            if (ns > 0) {
+                int rank = 0;
+                uint64_t it = sm;
+                while (it) {
+                    int j = __ffsll((unsigned long long)it) - 1;
+                    it &= it - 1;
+                    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)kc, j);
+                    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(kc >> 32), j);
+                    uint64_t kj = ((uint64_t)hi << 32) | lo;
+                    rank += kj < kc ? 1 : 0;
+                }
+                if (val) s.tmp[rank] = kc;
+                wave_sync();
+                const int nqn = qn + ns < Leff ? qn + ns : Leff;
+#pragma unroll
+                for (int j = 0; j < QS; ++j) {
+                    int e = j * 64 + lane;
+                    if (e < qn) {
+                        uint64_t ke = qa[e];
+                        int np = e + lower_bound_keys(s.tmp, ns, key_mask(ke));
+                        if (np < Leff) qb[np] = ke;
+                    }
+                }
+                if (val && lb + rank < Leff) qb[lb + rank] = kc;
+                wave_sync();
+                uint64_t *t = qa;
+                qa = qb;
+                qb = t;
+                qn = nqn;
+            }
+            if (cut < 64) break;
+        }
+    }
+
+    // ---- outputs: the first k of the beam
+    for (int e = lane; e < a.k; e += 64) {
+        uint32_t id = NONE;
+        float dist = __builtin_inff();
+        if (e < qn) {
+            uint64_t ke = qa[e];
+            id = key_id(ke);
+            dist = __builtin_sqrtf(key_dist(ke));
+        }
+        a.ids[(size_t)qi * a.k + e] = id;
+        a.dists[(size_t)qi * a.k + e] = dist;
+    }
+    if (lane == 0) {
+        if (a.hops) a.hops[qi] = hops;
+        if (a.ndc) a.ndc[qi] = ndc;
+    }
+}
+
+template <int G, int RND, bool VEC, int QS, int UB>
+__global__ __launch_bounds__(256) void search_kernel(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int64_t qi = (int64_t)blockIdx.x * wpb + wave;
+    if (qi >= a.nq) return;  // waves never synchronise with each other
+    const int qcap = 64 * QS;
+    unsigned char *base = smem + (size_t)wave * wave_lds_bytes(qcap, a.vlog2);
+    WaveLds s;
+    s.qa = reinterpret_cast<uint64_t *>(base);
+    s.qb = s.qa + qcap;
+    s.tmp = s.qb + qcap;
+    s.dsc = reinterpret_cast<float *>(s.tmp + 64);
+    s.cid = reinterpret_cast<uint32_t *>(s.dsc + 64);
+    s.vis = s.cid + 64;
+    beam_query<G, RND, VEC, QS, UB>(a, qi, s);
+}
+
+using KernelFn = void (*)(SearchArgs);
+
+template <int G, int RND, bool VEC>
+KernelFn pick_qs(int qs)
+{
+    constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : 8;
+    switch (qs) {
+    case 1: return search_kernel<G, RND, VEC, 1, UB>;
+    case 2: return search_kernel<G, RND, VEC, 2, UB>;
+    case 4: return search_kernel<G, RND, VEC, 4, UB>;
+    default: return search_kernel<G, RND, VEC, 8, UB>;
+    }
+}
+
+template <bool VEC>
+KernelFn pick_kernel(int d, int qs)
+{
+    if (d <= 32) return pick_qs<8, 1, VEC>(qs);
+    if (d <= 64) return pick_qs<16, 1, VEC>(qs);
+    int rnd = (d + 127) / 128;
+    if (rnd <= 1) return pick_qs<32, 1, VEC>(qs);
+    if (rnd <= 2) return pick_qs<32, 2, VEC>(qs);
+    if (rnd <= 4) return pick_qs<32, 4, VEC>(qs);
+    if (rnd <= 8) return pick_qs<32, 8, VEC>(qs);
+    if (rnd <= 16) return pick_qs<32, 16, VEC>(qs);
+    return pick_qs<32, 32, VEC>(qs);
+}
+
+}  // namespace
+
+int search_default_vlog2(int Leff)
+{
+    return Leff <= 64 ? 11 : 12;
+}
+
+size_t search_lds_per_wave(int Leff, int vlog2)
+{
+    int qs = Leff <= 64 ? 1 : Leff <= 128 ? 2 : Leff <= 256 ? 4 : 8;
+    return wave_lds_bytes(64 * qs, vlog2);
+}
+
+hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
+{
+    if (a.nq == 0) return hipSuccess;
+    const int qs = a.Leff <= 64 ? 1 : a.Leff <= 128 ? 2 : a.Leff <= 256 ? 4 : 8;
+    const bool vec = (a.d % 4 == 0) && ((uintptr_t)a.points % 16 == 0) &&
+                     (a.query_ids || (uintptr_t)a.queries % 16 == 0);
+    KernelFn fn = vec ? pick_kernel<true>(a.d, qs) : pick_kernel<false>(a.d, qs);
+    // the visited table may be shrunk to keep a wave within 64 KB of LDS
+    // (it only changes how often a distance is recomputed, never the results)
+    SearchArgs b = a;
+    while (b.vlog2 > 6 && wave_lds_bytes(64 * qs, b.vlog2) > 64 * 1024) --b.vlog2;
+    const size_t per_wave = wave_lds_bytes(64 * qs, b.vlog2);
+    int wpb = 4;
+    while (wpb > 1 && (size_t)wpb * per_wave > 64 * 1024) wpb >>= 1;
+    const int64_t blocks = (a.nq + wpb - 1) / wpb;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), (unsigned)(wpb * per_wave),
+                       stream, b);
+    return hipGetLastError();
+}
+
+}  // namespace cng

@@ -1,0 +1,28 @@
+"""Helpers shared by the GPU tests (host <-> device marshalling only)."""
+import numpy as np
+import torch
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def dev_ids(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(DEV)
+
+
+def host_ids(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def f32_of(d64):
+    """Oracle float64 values that hold float32 results -> float32."""
+    return np.asarray(d64).astype(np.float32)
+
+
+def same_f32(a, b):
+    a = np.asarray(a, np.float32)
+    b = np.asarray(b, np.float32)
+    return a.shape == b.shape and np.array_equal(a.view(np.uint32), b.view(np.uint32))

@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: the library loads, exports every function the
+header declares, and rejects invalid arguments before any device work."""
+import ctypes as C
+
+import pytest
+
+import paper_2510_05975_amd as cng
+from paper_2510_05975_amd import _lib
+
+
+def test_exports_every_declared_symbol():
+    L = cng.lib()
+    names = _lib.header_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert cng.version().startswith("cng-gfx950")
+
+
+def _params(**kw):
+    p = dict(R=32, extra=1, C=128, alpha=1.2, tau=0.0, flags=1, Lc=0, band=0, visited_log2=0)
+    p.update(kw)
+    return _lib.BuildParams(*[p[f] for f, _ in _lib.BuildParams._fields_])
+
+
+@pytest.mark.parametrize("bad", [dict(R=0), dict(extra=-1), dict(C=0), dict(alpha=0.0),
+                                 dict(alpha=float("nan")), dict(tau=-1.0), dict(Lc=-1),
+                                 dict(visited_log2=3), dict(visited_log2=20)])
+def test_build_params_rejected(bad):
+    nb = C.c_size_t(0)
+    st = cng.lib().cng_build_workspace_size(1000, 32, C.byref(_params(**bad)), C.byref(nb))
+    assert st == -1
+    assert cng.lib().cng_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("bad", [dict(R=200, extra=100), dict(band=1024), dict(C=300), dict(Lc=1000)])
+def test_build_params_unsupported(bad):
+    nb = C.c_size_t(0)
+    st = cng.lib().cng_build_workspace_size(100000, 32, C.byref(_params(**bad)), C.byref(nb))
+    assert st == -4
+
+
+def test_build_sizes():
+    nb = C.c_size_t(0)
+    assert cng.lib().cng_build_workspace_size(1, 32, C.byref(_params()), C.byref(nb)) == -1  # n < 2
+    assert cng.lib().cng_build_workspace_size(1000, 0, C.byref(_params()), C.byref(nb)) == -1
+    assert cng.lib().cng_build_workspace_size(1000, 5000, C.byref(_params()), C.byref(nb)) == -1
+    assert cng.lib().cng_build_workspace_size(10000, 32, C.byref(_params()), C.byref(nb)) == 0
+    small = nb.value
+    assert cng.lib().cng_build_workspace_size(20000, 32, C.byref(_params()), C.byref(nb)) == 0
+    assert nb.value > small > 0
+    assert cng.lib().cng_last_error().decode() == ""
+
+
+def test_search_rejects_before_launch():
+    L = cng.lib()
+    fake = C.c_void_p(0x1000)
+    # k = 0
+    assert L.cng_search(fake, 100, 8, fake, 4, fake, 1, 0, 10, fake, 1, fake, fake, None, None, 0,
+                        None) == -1
+    # max(L, k) > 512
+    assert L.cng_search(fake, 100, 8, fake, 4, fake, 1, 10, 600, fake, 1, fake, fake, None, None,
+                        0, None) == -4
+    # n_entries neither 1 nor nq
+    assert L.cng_search(fake, 100, 8, fake, 4, fake, 5, 10, 10, fake, 3, fake, fake, None, None, 0,
+                        None) == -1
+    # W too large
+    assert L.cng_search(fake, 100, 8, fake, 300, fake, 1, 10, 10, fake, 1, fake, fake, None, None,
+                        0, None) == -4
+    # NULL queries
+    assert L.cng_search(fake, 100, 8, fake, 4, None, 1, 10, 10, fake, 1, fake, fake, None, None, 0,
+                        None) == -1
+    # nq = 0 is a no-op
+    assert L.cng_search(fake, 100, 8, fake, 4, None, 0, 10, 10, fake, 1, fake, fake, None, None, 0,
+                        None) == 0
+
+
+def test_other_stages_reject():
+    L = cng.lib()
+    fake = C.c_void_p(0x1000)
+    nb = C.c_size_t(0)
+    assert L.cng_knn_workspace_size(10, 10, 8, 0, 0, C.byref(nb)) == -1
+    assert L.cng_knn_workspace_size(10, 10, 8, 300, 0, C.byref(nb)) == -4
+    # exclude_self with different row and column arrays
+    assert L.cng_knn(fake, 10, C.c_void_p(0x2000), 10, 8, 4, 1, 0, fake, fake, fake, 1 << 30, None,
+                     None) == -1
+    assert L.cng_prune(fake, 10, 8, fake, fake, 4, 5, 4, 1.2, 0.0, fake, None) == -1  # W < R
+    assert L.cng_prune(fake, 10, 8, fake, fake, 4, 4, 4, -1.0, 0.0, fake, None) == -1
+    assert L.cng_connect(fake, 10, 8, fake, 4, 10, 8, 0, fake, 1 << 30, None, None, None) == -1
+    # workspace too small
+    assert L.cng_entry_point(fake, 10, 8, fake, fake, 1, None) == -2

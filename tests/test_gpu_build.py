@@ -1,0 +1,151 @@
+"""GPU build stages against the CPU oracle (bit for bit in the fixed-order
+float32 mode): entry point, exact candidate lists, pruning (Eq. (1),
+Algorithm 2), connectivity and the whole build."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2510_05975_amd as cng
+import workloads
+from gpu_util import dev, dev_ids, f32_of, host_ids, same_f32
+
+pytestmark = pytest.mark.gpu
+
+
+# ---------------------------------------------------------------- entry point
+@pytest.mark.parametrize("case", [(1, 10000), (2, 9000), (3, 3000), (4, 5000)])
+def test_entry_point(case):
+    cfg, n = case
+    x, _ = workloads.generate(cfg, n=n, nq=1)
+    assert cng.entry_point(dev(x)) == oracle.medoid(x)
+
+
+def test_entry_point_tie_and_tiny():
+    x = np.array([[1.0], [-1.0], [3.0], [-3.0]], np.float32)
+    assert cng.entry_point(dev(x)) == 0
+    x = np.array([[5.0, 1.0]], np.float32)
+    assert cng.entry_point(dev(x)) == 0
+
+
+# ---------------------------------------------------------------- candidates
+def gpu_knn(rows, cols, C, exclude_self, band=0):
+    r = dev(rows)
+    c = r if exclude_self else dev(cols)
+    ids, D, ovf = cng.knn(r, c, C, exclude_self=exclude_self, band=band)
+    torch.cuda.synchronize()
+    return host_ids(ids), D.cpu().numpy(), ovf
+
+
+@pytest.mark.parametrize("case", [(1, 3000, 64), (1, 10000, 64), (2, 4000, 128), (3, 1500, 192),
+                                  (4, 3000, 128)])
+def test_knn_points(case):
+    cfg, n, C = case
+    print(f"knn cfg{cfg} n={n} C={C}", flush=True)
+    x, _ = workloads.generate(cfg, n=n, nq=1)
+    ids, D, _ = gpu_knn(x, x, C, True)
+    oids, oD = oracle.knn(x, x, C, exclude_self=True)
+    assert (ids == oids).all(), np.argwhere(ids != oids)[:5]
+    assert same_f32(D, f32_of(oD))
+
+
+def test_knn_queries_vs_points_ragged():
+    x, q = workloads.generate(1, n=1999, nq=77)
+    ids, D, _ = gpu_knn(q, x, 10, False)
+    oids, oD = oracle.knn(q, x, 10)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+@pytest.mark.parametrize("d", [1, 3, 7, 33, 100, 129, 300])
+def test_knn_dims(d):
+    x, _ = workloads.uniform_cube(700, 1, d, seed=d)
+    ids, D, _ = gpu_knn(x, x, 16, True)
+    oids, oD = oracle.knn(x, x, 16, exclude_self=True)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+def test_knn_forced_band_overflow():
+    """A band too small for the candidates sends rows to the exhaustive path."""
+    x, _ = workloads.generate(1, n=3000, nq=1)
+    ids, D, ovf = gpu_knn(x, x, 64, True, band=64)
+    assert ovf > 0
+    oids, oD = oracle.knn(x, x, 64, exclude_self=True)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+def test_knn_fewer_points_than_C_and_duplicates():
+    x, _ = workloads.uniform_cube(40, 1, 8, seed=3)
+    x[5] = x[9]
+    x[17] = x[9]
+    ids, D, _ = gpu_knn(x, x, 64, True)
+    oids, oD = oracle.knn(x, x, 64, exclude_self=True)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+    assert (ids[:, 39:] == oracle.NONE).all()
+
+
+# ---------------------------------------------------------------- pruning
+@pytest.mark.parametrize("alpha,tau", [(1.2, 0.0), (1.0, 0.0), (0.9, 0.0), (1.5, 0.3), (2.0, 0.0)])
+def test_prune(alpha, tau):
+    x, _ = workloads.generate(1, n=4000, nq=1)
+    cand, D = oracle.knn(x, x, 64, exclude_self=True)
+    oadj = oracle.prune(x, cand, D, R=24, alpha=alpha, tau=tau, width=25)
+    adj = cng.prune(dev(x), dev_ids(cand), dev(f32_of(D)), 24, alpha, tau, width=25)
+    torch.cuda.synchronize()
+    assert (host_ids(adj) == oadj).all()
+
+
+def test_prune_integer_ties_need_fp64():
+    """Integer data has exact ties in Eq. (1) (e.g. alpha^2 * D(u,v) == D(p,u));
+    the float64 re-decision must match the oracle."""
+    x, _ = workloads.generate(2, n=3000, nq=1)
+    cand, D = oracle.knn(x, x, 128, exclude_self=True)
+    for alpha in (1.2, 1.5, 2.0):
+        oadj = oracle.prune(x, cand, D, R=32, alpha=alpha, width=33)
+        adj = cng.prune(dev(x), dev_ids(cand), dev(f32_of(D)), 32, alpha, 0.0, width=33)
+        torch.cuda.synchronize()
+        assert (host_ids(adj) == oadj).all()
+
+
+@pytest.mark.parametrize("d", [1, 5, 64, 129, 960])
+def test_prune_dims(d):
+    x, _ = workloads.uniform_cube(500, 1, d, seed=d)
+    cand, D = oracle.knn(x, x, 32, exclude_self=True)
+    oadj = oracle.prune(x, cand, D, R=12, alpha=1.2)
+    adj = cng.prune(dev(x), dev_ids(cand), dev(f32_of(D)), 12, 1.2)
+    torch.cuda.synchronize()
+    assert (host_ids(adj) == oadj).all()
+
+
+# ---------------------------------------------------------------- connectivity
+def test_connect():
+    x, _ = workloads.generate(1, n=5000, nq=1)
+    cand, D = oracle.knn(x, x, 32, exclude_self=True)
+    pruned = oracle.prune(x, cand, D, R=12, alpha=1.2, width=13)
+    s = oracle.medoid(x)
+    oadj, oadded, orounds = oracle.connect(x, pruned, s, Lc=32)
+    assert oadded > 0
+    a = dev_ids(pruned)
+    rounds, added = cng.connect(dev(x), a, s, 32)
+    assert (host_ids(a) == oadj).all()
+    assert (rounds, added) == (orounds, oadded)
+
+
+def test_connect_capacity_error():
+    x = np.array([[0.0], [1.0], [2.0], [10.0]], np.float32)
+    adj = np.array([[1], [2], [0], [2]], np.uint32)
+    with pytest.raises(cng.CngError) as ei:
+        cng.connect(dev(x), dev_ids(adj), 0, 4)
+    assert ei.value.status == -5
+
+
+# ---------------------------------------------------------------- whole build
+@pytest.mark.parametrize("case", [(1, 10000, 24, 64), (2, 5000, 32, 128), (4, 4000, 32, 128)])
+def test_build_bit_exact(case):
+    cfg, n, R, C = case
+    print(f"build cfg{cfg} n={n}", flush=True)
+    x, _ = workloads.generate(cfg, n=n, nq=1)
+    oadj, oe, oadded = oracle.build(x, R, C, 1.2)
+    g = cng.build(dev(x), R, C, 1.2)
+    assert g.entry == oe
+    assert (host_ids(g.adj) == oadj).all()
+    assert g.stats["connect_added"] == oadded
