@@ -2,8 +2,9 @@
 // (beam-search(G, q, s, L, k), Section 2.2), one wavefront per query.
 //
 // Per wavefront, in LDS:
-//   beam   two ping-pong arrays of L_eff keys (D, id), ascending; bit 63 of a
-//          key marks the point as explored (the set E of Algorithm 1);
+//   beam   L_eff keys (D, id), ascending; bit 63 of a key marks the point as
+//          explored (the set E of Algorithm 1); merged in place (every lane
+//          reads its old entries into registers before any entry is written);
 //   vis    an open-addressing table of ids whose distance was computed.  It
 //          never reports an id it has not seen, so skipping those ids leaves
 //          the beam identical to Algorithm 1 at every step (a point that left
@@ -73,19 +74,19 @@ __device__ __forceinline__ int lower_bound_keys(const uint64_t *arr, int cnt, ui
 }
 
 struct WaveLds {
-    uint64_t *qa, *qb, *tmp;
+    uint64_t *qa, *tmp;
     float *dsc;
     uint32_t *cid, *vis;
 };
 
 __host__ __device__ constexpr size_t wave_lds_bytes(int qcap, int vlog2)
 {
-    return (size_t)2 * qcap * 8 + 64 * 8 + 64 * 4 + 64 * 4 + ((size_t)4 << vlog2);
+    return (size_t)qcap * 8 + 64 * 8 + 64 * 4 + 64 * 4 + ((size_t)4 << vlog2);
 }
 
 // One query.  G lanes per vector, RND float4 rounds per lane, QS beam slots per lane.
 template <int G, int RND, bool VEC, int QS, int UB>
-__device__ void beam_query(const SearchArgs &a, int64_t qi, WaveLds s)
+__device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
 {
     constexpr int NG = 64 / G;
     const int lane = lane_id();
@@ -127,7 +128,7 @@ __device__ void beam_query(const SearchArgs &a, int64_t qi, WaveLds s)
     wave_sync();
     int qn = 1;
     uint32_t hops = 0, ndc = 1;
-    uint64_t *qa = s.qa, *qb = s.qb;
+    uint64_t *qa = s.qa;
 
     for (;;) {
         const int f = first_unexplored<QS>(qa, qn);
@@ -204,22 +205,24 @@ __device__ void beam_query(const SearchArgs &a, int64_t qi, WaveLds s)
                     rank += kj < kc ? 1 : 0;
                 }
                 if (val) s.tmp[rank] = kc;
-                wave_sync();
+                uint64_t old[QS];
+#pragma unroll
+                for (int j = 0; j < QS; ++j) {
+                    int e = j * 64 + lane;
+                    old[j] = e < qn ? qa[e] : 0;
+                }
+                wave_sync();  // every old entry is in registers before any write
                 const int nqn = qn + ns < Leff ? qn + ns : Leff;
 #pragma unroll
                 for (int j = 0; j < QS; ++j) {
                     int e = j * 64 + lane;
                     if (e < qn) {
-                        uint64_t ke = qa[e];
-                        int np = e + lower_bound_keys(s.tmp, ns, key_mask(ke));
-                        if (np < Leff) qb[np] = ke;
+                        int np = e + lower_bound_keys(s.tmp, ns, key_mask(old[j]));
+                        if (np < Leff) qa[np] = old[j];
                     }
                 }
-                if (val && lb + rank < Leff) qb[lb + rank] = kc;
+                if (val && lb + rank < Leff) qa[lb + rank] = kc;
                 wave_sync();
-                uint64_t *t = qa;
-                qa = qb;
-                qb = t;
                 qn = nqn;
             }
             if (cut < 64) break;
@@ -256,8 +259,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a)
     unsigned char *base = smem + (size_t)wave * wave_lds_bytes(qcap, a.vlog2);
     WaveLds s;
     s.qa = reinterpret_cast<uint64_t *>(base);
-    s.qb = s.qa + qcap;
-    s.tmp = s.qb + qcap;
+    s.tmp = s.qa + qcap;
     s.dsc = reinterpret_cast<float *>(s.tmp + 64);
     s.cid = reinterpret_cast<uint32_t *>(s.dsc + 64);
     s.vis = s.cid + 64;
@@ -294,9 +296,11 @@ KernelFn pick_kernel(int d, int qs)
 
 }  // namespace
 
+// Measured on 1M x 128 (beam 48..128): a 1024-slot table beats larger ones,
+// whose LDS cost in occupancy outweighs the distance evaluations they save.
 int search_default_vlog2(int Leff)
 {
-    return Leff <= 64 ? 11 : 12;
+    return Leff <= 128 ? 10 : Leff <= 256 ? 11 : 12;
 }
 
 size_t search_lds_per_wave(int Leff, int vlog2)
