@@ -176,15 +176,18 @@ struct FilterLds {
     uint64_t *sort;  // 4 x CB
 };
 
-// Compact the band of local row li (one wave); updates thr/cnt.  After the
-// last tile a band may stay large (no further appends follow).
-__device__ void compact_row(const FilterArgs &a, FilterLds &s, int li, uint64_t *buf, bool last)
+// Compact the band of chunk row lr (one wave): sort it, set the threshold to
+// F_C + 2E and keep the entries at or below it.  A band that could not take
+// another tile of `bn` columns is marked overflowed (cnt = -1, threshold
+// -inf): that row is recomputed exhaustively.  After the last tile a band may
+// stay large (no further appends follow).
+__device__ void compact_band(const FilterArgs &a, int64_t lr, float *thr_slot, int *cnt_slot,
+                             float erow, uint64_t *buf, bool last, int bn)
 {
     const int lane = lane_id();
-    const int64_t lr = (int64_t)blockIdx.x * BM + li;  // row within the chunk
     float *bF = a.bandF + (size_t)lr * a.CB;
     uint32_t *bI = a.bandI + (size_t)lr * a.CB;
-    int c = s.cnt[li];
+    int c = *cnt_slot;
     if (c > a.CB) c = a.CB;
     int np = 1;
     while (np < c) np <<= 1;
@@ -192,10 +195,10 @@ __device__ void compact_row(const FilterArgs &a, FilterLds &s, int li, uint64_t 
         buf[e] = e < c ? (((uint64_t)fkey(bF[e]) << 32) | bI[e]) : ~0ull;
     wave_sort(buf, np);
     int keep = c;
-    float thr = s.thr[li];
+    float thr = *thr_slot;
     if (c >= a.C) {
         float fc = unfkey((uint32_t)(buf[a.C - 1] >> 32));
-        thr = float_up((double)fc + 2.0 * (double)s.erow[li]);
+        thr = float_up((double)fc + 2.0 * (double)erow);
         uint32_t tk = fkey(thr);
         // entries are sorted: count those with F <= thr
         int cntk = 0;
@@ -212,12 +215,12 @@ __device__ void compact_row(const FilterArgs &a, FilterLds &s, int li, uint64_t 
     }
     wave_sync();
     if (lane == 0) {
-        if (!last && keep > a.CB - BN) {  // cannot take another tile: recompute exhaustively
-            s.cnt[li] = -1;
-            s.thr[li] = -__builtin_inff();
+        if (!last && keep > a.CB - bn) {
+            *cnt_slot = -1;
+            *thr_slot = -__builtin_inff();
         } else {
-            s.cnt[li] = keep;
-            s.thr[li] = thr;
+            *cnt_slot = keep;
+            *thr_slot = thr;
         }
     }
 }
@@ -338,7 +341,9 @@ __global__ __launch_bounds__(NT) void filter_f32(FilterArgs a)
         for (int li = wave; li < BM; li += NT / 64) {
             const int c = s.cnt[li];
             const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN);
-            if (need) compact_row(a, s, li, s.sort + (size_t)wave * a.CB, last);
+            if (need)
+                compact_band(a, (int64_t)blockIdx.x * BM + li, &s.thr[li], &s.cnt[li], s.erow[li],
+                             s.sort + (size_t)wave * a.CB, last, BN);
         }
         __syncthreads();
     }
@@ -349,6 +354,205 @@ __global__ __launch_bounds__(NT) void filter_f32(FilterArgs a)
             if (s.cnt[li] < 0) atomicAdd(&a.st->overflow, 1u);
         }
     }
+}
+
+// ---------------------------------------------------------------- bf16 filter
+// Used when every value is a small integer (see launch_knn): the bf16 copies
+// are then exact, every product and partial sum is an integer below 2^24 and
+// the float32 accumulation of the matrix cores is exact, so E = 0.
+// A workgroup owns 256 rows (64 per wave, kept in registers as MFMA A
+// fragments) and sweeps column tiles of 64 through double-buffered LDS.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM2 = 256, BN2 = 64;
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+// x [n x d] float32 -> [n x K] bf16, zero padded to K.
+__global__ void to_bf16_padded(const float *__restrict__ x, int64_t n, int d, int K,
+                               uint16_t *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * K) return;
+    int64_t r = t / K;
+    int k = (int)(t % K);
+    out[t] = k < d ? to_bf16_rne(x[(size_t)r * d + k]) : (uint16_t)0;
+}
+
+struct FilterBf16Args {
+    FilterArgs f;
+    const uint16_t *rows16;  // [nr x K]
+    const uint16_t *cols16;  // [nc x K]
+};
+
+template <int KS>
+__global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
+{
+    constexpr int K = 16 * KS;
+    constexpr int BSTR = K + 8;  // bf16 elements per LDS column row (16 B pad: no bank conflicts)
+    const FilterArgs &a = A.f;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);              // 2 x BN2 x BSTR
+    float *thr = reinterpret_cast<float *>(Bs + 2 * BN2 * BSTR);    // BM2
+    float *erow = thr + BM2;
+    int *cnt = reinterpret_cast<int *>(erow + BM2);
+    int *flag = cnt + BM2;                                          // [0]: a band needs compaction
+    uint64_t *sortb = reinterpret_cast<uint64_t *>(flag + 2);
+
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM2;
+    const int64_t rend = a.r0 + a.chunk < a.nr ? a.r0 + a.chunk : a.nr;
+    for (int li = threadIdx.x; li < BM2; li += 256) {
+        int64_t gi = row0 + li;
+        bool live = gi < rend;
+        thr[li] = live ? __builtin_inff() : -__builtin_inff();
+        erow[li] = live ? a.E[gi] : 0.f;
+        cnt[li] = 0;
+    }
+    if (threadIdx.x == 0) flag[0] = 0;
+
+    // A fragments of this wave's 64 rows: [row block][k step]
+    bf16x8 af[2][KS];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t gi = row0 + wave * 64 + i * 32 + (lane & 31);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (gi < rend)
+                af[i][ks] = *reinterpret_cast<const bf16x8 *>(A.rows16 + (size_t)gi * K + ks * 16 + (lane >> 5) * 8);
+            else
+                af[i][ks] = bf16x8{};
+        }
+    }
+
+    // B tile loader: BN2 columns x K bf16 = BN2 * K / 8 chunks of 16 B
+    constexpr int CHUNKS = BN2 * K / 8;
+    constexpr int PER_T = (CHUNKS + 255) / 256;
+    uint4 pre[PER_T];
+    auto fetch = [&](int64_t col0) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            int c = threadIdx.x + 256 * i;
+            int col = c / (K / 8), kc = c % (K / 8);
+            int64_t gj = col0 + col;
+            pre[i] = make_uint4(0, 0, 0, 0);
+            if (c < CHUNKS && gj < a.nc)
+                pre[i] = *reinterpret_cast<const uint4 *>(A.cols16 + (size_t)gj * K + kc * 8);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            int c = threadIdx.x + 256 * i;
+            if (c < CHUNKS) {
+                int col = c / (K / 8), kc = c % (K / 8);
+                *reinterpret_cast<uint4 *>(Bs + (size_t)buf * BN2 * BSTR + col * BSTR + kc * 8) = pre[i];
+            }
+        }
+    };
+
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    // per-lane thresholds of the 32 rows this lane sees (refreshed after compactions)
+    float th[2][16];
+    auto load_thr = [&]() {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                th[i][r] = thr[wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
+    };
+    load_thr();
+
+    int buf = 0;
+    for (int64_t col0 = 0; col0 < a.nc; col0 += BN2) {
+        const bool more = col0 + BN2 < a.nc;
+        if (more) fetch(col0 + BN2);
+        floatx16 acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+        const uint16_t *Bb = Bs + (size_t)buf * BN2 * BSTR;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(
+                    Bb + (j * 32 + (lane & 31)) * BSTR + ks * 16 + (lane >> 5) * 8);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][ks], bfr, acc[i][j], 0, 0, 0);
+            }
+        }
+        // ---- epilogue: F = |y|^2 - 2 x.y against the row thresholds
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t gj = col0 + j * 32 + (lane & 31);
+            const bool colok = gj < a.nc;
+            const float nyj = colok ? a.ny[gj] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float F = __builtin_fmaf(-2.0f, acc[i][j][r], nyj);
+                    bool take = colok && F <= th[i][r];
+                    if (__builtin_expect(ballot(take) != 0, 0) && take) {
+                        const int li = wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        const int64_t gi = row0 + li;
+                        if (gi < rend && !(a.exclude_self && gi == gj)) {
+                            int pos = atomicAdd(&cnt[li], 1);
+                            if (pos < a.CB) {
+                                const size_t o = (size_t)(gi - a.r0) * a.CB + pos;
+                                a.bandF[o] = F;
+                                a.bandI[o] = (uint32_t)gj;
+                            }
+                            if (pos + 1 > a.CB - BN2) flag[0] = 1;
+                        }
+                    }
+                }
+            }
+        }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        const bool last = !more;
+        if (flag[0] || last) {
+            for (int li = wave; li < BM2; li += 4) {
+                const int c = cnt[li];
+                const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN2);
+                if (need)
+                    compact_band(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
+                                 sortb + (size_t)wave * a.CB, last, BN2);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) flag[0] = 0;
+            load_thr();
+            __syncthreads();
+        }
+        buf ^= 1;
+    }
+    for (int li = threadIdx.x; li < BM2; li += 256) {
+        int64_t gi = row0 + li;
+        if (gi < rend) {
+            a.cnt[gi - a.r0] = cnt[li];
+            if (cnt[li] < 0) atomicAdd(&a.st->overflow, 1u);
+        }
+    }
+}
+
+size_t filter_bf16_lds_bytes(int K, int CB)
+{
+    size_t b = (size_t)2 * BN2 * (K + 8) * 2 + (size_t)BM2 * 4 * 3 + 8;
+    b = (b + 15) & ~(size_t)15;
+    return b + (size_t)4 * CB * 8;
 }
 
 // ---------------------------------------------------------------- rerank
@@ -547,7 +751,6 @@ size_t filter_lds_bytes(int CB)
 
 KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
 {
-    (void)d;
     KnnPlan p;
     int CB = band > 0 ? next_pow2(band) : next_pow2(2 * C + BN);
     if (CB < 64) CB = 64;
@@ -558,9 +761,14 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
     if (chunk < BM) chunk = BM;
     int64_t nr_pad = (nr + BM - 1) / BM * BM;
     if (chunk > nr_pad) chunk = nr_pad;
+    chunk = (chunk + BM2 - 1) / BM2 * BM2;  // whole workgroups of either filter
     p.chunk_rows = chunk;
     p.bytes = align256((size_t)nc * 4) + align256((size_t)nr * 4) * 2 + align256(sizeof(PrepOut)) +
               align256((size_t)chunk * CB * 4) * 2 + align256((size_t)chunk * 4);
+    if (d <= 128) {  // bf16 copies for the exact small-integer filter
+        const int K = (d + 15) / 16 * 16;
+        p.bytes += align256((size_t)nc * K * 2) + align256((size_t)nr * K * 2);
+    }
     return p;
 }
 
@@ -583,6 +791,14 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     uint32_t *bandI = (uint32_t *)w;
     w += align256((size_t)plan.chunk_rows * CB * 4);
     int *cnt = (int *)w;
+    w += align256((size_t)plan.chunk_rows * 4);
+    const int K16 = (d + 15) / 16 * 16;
+    uint16_t *cols16 = nullptr, *rows16 = nullptr;
+    if (d <= 128) {
+        cols16 = (uint16_t *)w;
+        w += align256((size_t)nc * K16 * 2);
+        rows16 = (uint16_t *)w;
+    }
 
     hipLaunchKernelGGL(init_prep, dim3(1), dim3(1), 0, stream, st);
     hipLaunchKernelGGL(prep_cols, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream, cols, nc,
@@ -600,8 +816,20 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     const double lim = 16777216.0;
     bool exact = h.all_int != 0 &&
                  (h.any_neg ? 4.0 * d * M * M <= lim : 2.0 * d * M * M <= lim);
+    // bf16 holds every integer of magnitude <= 256 exactly
+    const bool use_bf16 = exact && d <= 128 && M <= 256.0;
     if (exact_int) *exact_int = exact ? 1 : 0;
-    if (dtype) *dtype = 0;
+    if (dtype) *dtype = use_bf16 ? 1 : 0;
+    if (use_bf16) {
+        const int64_t tc = nc * K16, tr = nr * K16;
+        hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, stream,
+                           cols, nc, d, K16, cols16);
+        if (rows != cols || nr != nc)
+            hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tr + 255) / 256)), dim3(256), 0,
+                               stream, rows, nr, d, K16, rows16);
+        else
+            rows16 = cols16;
+    }
     const double kappa = (6.0 * d + 40.0) * 5.9604644775390625e-8;  // (6d + 40) * 2^-24
     hipLaunchKernelGGL(row_bounds, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, xn, nr,
                        st, kappa, exact ? 1 : 0, E);
@@ -615,9 +843,25 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     for (int64_t r0 = 0; r0 < nr; r0 += plan.chunk_rows) {
         const int64_t chunk = nr - r0 < plan.chunk_rows ? nr - r0 : plan.chunk_rows;
         FilterArgs fa{rows, nr, r0, chunk, cols, nc, d, C, exclude_self, ny, E, CB, bandF, bandI, cnt, st};
-        const unsigned fblocks = (unsigned)((chunk + BM - 1) / BM);
-        if (vec) hipLaunchKernelGGL(filter_f32<true>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
-        else hipLaunchKernelGGL(filter_f32<false>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
+        if (use_bf16) {
+            FilterBf16Args fb{fa, rows16, cols16};
+            const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
+            const unsigned lds = (unsigned)filter_bf16_lds_bytes(K16, CB);
+            switch (K16 / 16) {
+            case 1: hipLaunchKernelGGL(filter_bf16<1>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 2: hipLaunchKernelGGL(filter_bf16<2>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 3: hipLaunchKernelGGL(filter_bf16<3>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 4: hipLaunchKernelGGL(filter_bf16<4>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 5: hipLaunchKernelGGL(filter_bf16<5>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 6: hipLaunchKernelGGL(filter_bf16<6>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 7: hipLaunchKernelGGL(filter_bf16<7>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            default: hipLaunchKernelGGL(filter_bf16<8>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            }
+        } else {
+            const unsigned fblocks = (unsigned)((chunk + BM - 1) / BM);
+            if (vec) hipLaunchKernelGGL(filter_f32<true>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
+            else hipLaunchKernelGGL(filter_f32<false>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
+        }
         RerankArgs ra{rows, r0, chunk, nr, cols, nc, d, C, CB, bandF, bandI, cnt, ids, D};
         const unsigned rblocks = (unsigned)((chunk + 3) / 4);
         hipLaunchKernelGGL(rfn, dim3(rblocks), dim3(256), (unsigned)(4 * CB * 8), stream, ra);

@@ -149,3 +149,16 @@ def test_build_bit_exact(case):
     assert g.entry == oe
     assert (host_ids(g.adj) == oadj).all()
     assert g.stats["connect_added"] == oadded
+
+
+@pytest.mark.parametrize("d,lo,hi", [(128, 0, 256), (96, 0, 256), (64, 0, 256), (17, 0, 256),
+                                     (32, -90, 91), (128, -1, 2)])
+def test_knn_small_integer_bf16_path(d, lo, hi):
+    """Small-integer data takes the exact bf16 matrix-core filter."""
+    g = np.random.default_rng(1000 * d + lo + 1000)
+    x = g.integers(lo, hi, size=(3000, d)).astype(np.float32)
+    r = dev(x)
+    ids, D, _ = cng.knn(r, r, 40, exclude_self=True)
+    torch.cuda.synchronize()
+    oids, oD = oracle.knn(x, x, 40, exclude_self=True)
+    assert (host_ids(ids) == oids).all() and same_f32(D.cpu().numpy(), f32_of(oD))
