@@ -160,6 +160,40 @@ cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t 
                       const uint32_t *entries, int64_t n_entries, uint32_t *ids, float *dists,
                       uint32_t *hops, uint32_t *ndc, int32_t visited_log2, void *stream);
 
+/* ------------------------------------------------------------------ precision form */
+
+typedef enum {
+    CNG_F32 = 0,      /* float32 */
+    CNG_BF16 = 1,     /* bfloat16, round to nearest even */
+    CNG_FP8_E4M3 = 2  /* OCP fp8 E4M3 codes with one float32 scale per vector */
+} cng_dtype;
+
+/* Bytes of the stored copy of n vectors of dimension d in `dtype`. */
+size_t cng_quantized_bytes(int64_t n, int32_t d, int32_t dtype);
+
+/* Reduced-precision copy of points [n x d] float32 for scoring in the search.
+ *   CNG_BF16:     vecs [n x d] uint16 bf16 bits, each element rounded to nearest even.
+ *   CNG_FP8_E4M3: vecs [n x d] uint8 codes and scales [n] float32; per vector
+ *                 s = max|x| / 448 (1 if the vector is zero), code = E4M3 value
+ *                 nearest x / s (ties to even, saturating at +-448); an element
+ *                 stands for value(code) * s.
+ * Finite inputs; enqueues and returns. */
+cng_status cng_quantize(const float *points, int64_t n, int32_t d, int32_t dtype, void *vecs,
+                        float *scales, void *stream);
+
+/* Beam search (Algorithm 1) scoring the stored copy `vecs` (dtype as above,
+ * widened to float32 values, same fixed reduction order), then the converged
+ * beam of L_eff entries is re-ranked with float32 distances to `points` and
+ * the first k are returned: ids and dists are the float32-exact values for the
+ * returned points.  hops/ndc count the reduced-precision search only.  Other
+ * arguments as cng_search.  dtype CNG_F32 (vecs == points) is plain search. */
+cng_status cng_search_quantized(const float *points, const void *vecs, int32_t dtype,
+                                const float *scales, int64_t n, int32_t d, const uint32_t *adj,
+                                int32_t W, const float *queries, int64_t nq, int32_t k, int32_t L,
+                                const uint32_t *entries, int64_t n_entries, uint32_t *ids,
+                                float *dists, uint32_t *hops, uint32_t *ndc, int32_t visited_log2,
+                                void *stream);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Message of the last non-OK status on the calling thread ("" if none). */

@@ -68,6 +68,14 @@ def lib():
         L.orc_build.argtypes = [f32p, i64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                 C.c_double, C.c_int, C.c_int, C.c_int, u32p,
                                 C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
+        L.orc_round_bf16.restype = C.c_float
+        L.orc_round_bf16.argtypes = [C.c_float]
+        L.orc_round_e4m3.restype = C.c_float
+        L.orc_round_e4m3.argtypes = [C.c_float]
+        L.orc_dequantized.argtypes = [f32p, i64, C.c_int, C.c_int, f32p, C.c_void_p]
+        L.orc_search_rerank.argtypes = [f32p, C.c_void_p, i64, C.c_int, u32p, C.c_int, f32p, i64,
+                                        C.c_int, C.c_int, u32p, i64, C.c_int, u32p, f64p,
+                                        C.c_void_p, C.c_void_p]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -202,3 +210,46 @@ def reachable(adj, entry: int) -> np.ndarray:
         seen[nb] = True
         frontier = nb
     return seen
+
+
+BF16 = 1
+FP8 = 2
+
+
+def round_bf16(x: float) -> float:
+    return float(lib().orc_round_bf16(float(x)))
+
+
+def round_e4m3(x: float) -> float:
+    return float(lib().orc_round_e4m3(float(x)))
+
+
+def dequantized(points, dtype: int):
+    """float32 values of the bf16 (dtype 1) or fp8-E4M3 + per-vector scale
+    (dtype 2) copy of ``points`` -> (values [n, d], scales [n] or None)."""
+    points = _f32(points)
+    n, d = points.shape
+    out = np.empty_like(points)
+    scales = np.empty(n, np.float32) if dtype == FP8 else None
+    _check(lib().orc_dequantized(points, n, d, dtype, out,
+                                 scales.ctypes.data if scales is not None else None), "dequantized")
+    return out, scales
+
+
+def search_rerank(search_points, rerank_points, adj, queries, k: int, L: int, entries,
+                  mode: int = FP32):
+    """Beam search on ``search_points``; the final beam re-ranked with ``rerank_points``."""
+    sp, qs = _f32(search_points), _f32(queries)
+    rp = _f32(rerank_points) if rerank_points is not None else None
+    n, d = sp.shape
+    adj = np.ascontiguousarray(adj, np.uint32)
+    entries = np.ascontiguousarray(np.atleast_1d(entries), np.uint32)
+    nq = qs.shape[0]
+    ids = np.empty((nq, k), np.uint32)
+    dists = np.empty((nq, k), np.float64)
+    hops = np.empty(nq, np.uint32)
+    ndc = np.empty(nq, np.uint32)
+    _check(lib().orc_search_rerank(sp, rp.ctypes.data if rp is not None else None, n, d, adj,
+                                   adj.shape[1], qs, nq, k, L, entries, entries.size, mode, ids,
+                                   dists, hops.ctypes.data, ndc.ctypes.data), "search_rerank")
+    return ids, dists, hops, ndc

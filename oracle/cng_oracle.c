@@ -463,6 +463,120 @@ int orc_search_trace(const float *pts, int64_t n, int d, const uint32_t *adj, in
 }
 
 /* ------------------------------------------------------------------------- */
+/* Reduced-precision storage (the precision form of the search: vectors kept  */
+/* in bf16 or in fp8-E4M3 with one float32 scale per vector, candidates scored */
+/* from them, the final beam re-ranked with the float32 vectors).  These       */
+/* return the float32 value each stored element stands for.                    */
+/* ------------------------------------------------------------------------- */
+
+/* Nearest bfloat16 (8 significant bits), ties to even. */
+float orc_round_bf16(float x)
+{
+    if (x == 0.0f || !isfinite(x)) return x;
+    if (fabsf(x) < 0x1p-126f) return ldexpf(rintf(ldexpf(x, 133)), -133); /* subnormal step */
+    int e;
+    float m = frexpf(x, &e); /* x = m 2^e, 0.5 <= |m| < 1 */
+    return ldexpf(rintf(ldexpf(m, 8)), e - 8);
+}
+
+/* Nearest OCP fp8-E4M3 value (4 significant bits, exponent bias 7, no
+ * infinities, largest finite 448, subnormal step 2^-9), ties to even,
+ * saturating at +-448. */
+float orc_round_e4m3(float v)
+{
+    float a = fabsf(v), r;
+    if (!(a == a)) return v;
+    if (a >= 448.0f) r = 448.0f;
+    else if (a < 0x1p-6f) r = ldexpf(rintf(ldexpf(a, 9)), -9);
+    else {
+        int e;
+        float m = frexpf(a, &e);
+        r = ldexpf(rintf(ldexpf(m, 4)), e - 4);
+        if (r > 448.0f) r = 448.0f;
+    }
+    return copysignf(r, v);
+}
+
+/* Per-vector fp8 scale: s = max|x| / 448 (1 for an all-zero vector). */
+float orc_fp8_scale(const float *x, int d)
+{
+    float m = 0.0f;
+    for (int i = 0; i < d; ++i) m = fmaxf(m, fabsf(x[i]));
+    return m > 0.0f ? m / 448.0f : 1.0f;
+}
+
+/* dtype 1: bf16, 2: fp8-E4M3 with per-vector scale.  out [n x d] holds the
+ * float32 values the stored vectors represent (fp8: code value times scale). */
+int orc_dequantized(const float *pts, int64_t n, int d, int dtype, float *out, float *scales)
+{
+    if (n < 0 || d < 1 || (dtype != 1 && dtype != 2)) return ORC_EINVAL;
+    for (int64_t p = 0; p < n; ++p) {
+        const float *x = pts + (size_t)p * d;
+        float *o = out + (size_t)p * d;
+        if (dtype == 1) {
+            for (int i = 0; i < d; ++i) o[i] = orc_round_bf16(x[i]);
+        } else {
+            float sc = orc_fp8_scale(x, d);
+            if (scales) scales[p] = sc;
+            for (int i = 0; i < d; ++i) {
+                float scaled = x[i] / sc;
+                o[i] = orc_round_e4m3(scaled) * sc;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Beam search over `spts` (the stored, possibly reduced-precision vectors),
+ * then, when rpts is given, the final beam (all of its L entries) is re-ranked
+ * by distances to the float32 vectors rpts and the first k returned. */
+int orc_search_rerank(const float *spts, const float *rpts, int64_t n, int d, const uint32_t *adj,
+                      int R, const float *queries, int64_t nq, int k, int L,
+                      const uint32_t *entries, int64_t n_entries, int mode, uint32_t *ids,
+                      double *dists, uint32_t *hops, uint32_t *ndc)
+{
+    if (n < 1 || d < 1 || R < 1 || k < 1 || L < 1 || nq < 0) return ORC_EINVAL;
+    if (n_entries != 1 && n_entries != nq) return ORC_EINVAL;
+    for (int64_t e = 0; e < n_entries; ++e)
+        if ((int64_t)entries[e] >= n) return ORC_EINVAL;
+    int Leff = L > k ? L : k;
+    int cap = Leff + R + 1;
+    int fail = 0;
+#pragma omp parallel
+    {
+        orc_beam b;
+        int ok = beam_init(&b, n, cap);
+        orc_key *rk = (orc_key *)malloc(sizeof(orc_key) * (size_t)cap);
+        if (!ok || !rk) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < nq; ++i) {
+            if (!ok || !rk) continue;
+            const float *q = queries + (size_t)i * d;
+            uint32_t s = entries[n_entries == 1 ? 0 : i];
+            uint32_t h = 0, nd = 0;
+            int qn = beam_one(&b, spts, n, d, adj, R, q, s, Leff, mode, &h, &nd, NULL, 0, NULL);
+            for (int j = 0; j < qn; ++j) {
+                rk[j].id = b.id[j];
+                rk[j].D = rpts ? dist_mode(q, rpts + (size_t)b.id[j] * d, d, mode) : b.D[j];
+            }
+            qsort(rk, (size_t)qn, sizeof(orc_key), cmp_key);
+            for (int j = 0; j < k; ++j) {
+                ids[(size_t)i * k + j] = j < qn ? rk[j].id : ORC_NONE;
+                dists[(size_t)i * k + j] = j < qn ? delta_mode(rk[j].D, mode) : INFINITY;
+            }
+            if (hops) hops[i] = h;
+            if (ndc) ndc[i] = nd;
+        }
+        beam_free(&b);
+        free(rk);
+    }
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Connectivity (Alg. 3 phase 4).  The paper only says that edges are added   */
 /* from the traversal tree of s so that every point is reachable.  Reading,    */
 /* in rounds on a fixed snapshot of the graph:                                 */

@@ -1,7 +1,8 @@
 """MI355X (gfx950) alpha-CNG: exact-candidate alpha-convergent graph build and
 batched beam search behind the C ABI of libcng.so (include/cng.h)."""
-from ._lib import (NONE, CngError, Graph, build, connect, entry_point, knn, lib, prune, search,
-                   u32, version)
+from ._lib import (BF16, F32, FP8, NONE, CngError, Graph, Store, build, connect, entry_point, knn,
+                   lib, prune, quantize, search, search_quantized, u32, version)
 
-__all__ = ["NONE", "CngError", "Graph", "build", "connect", "entry_point", "knn", "lib", "prune",
-           "search", "u32", "version"]
+__all__ = ["BF16", "F32", "FP8", "NONE", "CngError", "Graph", "Store", "build", "connect",
+           "entry_point", "knn", "lib", "prune", "quantize", "search", "search_quantized", "u32",
+           "version"]

@@ -69,6 +69,10 @@ _SIGS = {
                               C.POINTER(i64)]),
     "cng_search": (C.c_int, [vp, i64, i32, vp, i32, vp, i64, i32, i32, vp, i64, vp, vp, vp, vp,
                              i32, vp]),
+    "cng_quantized_bytes": (sz, [i64, i32, i32]),
+    "cng_quantize": (C.c_int, [vp, i64, i32, i32, vp, vp, vp]),
+    "cng_search_quantized": (C.c_int, [vp, vp, i32, vp, i64, i32, vp, i32, vp, i64, i32, i32, vp,
+                                       i64, vp, vp, vp, vp, i32, vp]),
 }
 
 
@@ -235,6 +239,54 @@ def search(points: torch.Tensor, adj: torch.Tensor, queries: torch.Tensor, k: in
     _check("cng_search", lib().cng_search(_ptr(x), n, d, _ptr(adj), adj.shape[1], _ptr(q), nq, k, L,
                                           _ptr(entries), entries.numel(), _ptr(ids), _ptr(dists),
                                           _ptr(hops), _ptr(ndc), visited_log2, _stream()))
+    return ids, dists, hops, ndc
+
+
+F32, BF16, FP8 = 0, 1, 2
+
+
+@dataclass
+class Store:
+    """Reduced-precision copy of the base vectors (cng_quantize)."""
+    dtype: int
+    vecs: torch.Tensor          # uint16 bf16 bits / uint8 fp8 codes, [n, d]
+    scales: torch.Tensor | None  # fp8 only, [n] float32
+
+
+def quantize(points: torch.Tensor, dtype: int) -> Store:
+    x = _f32(points)
+    n, d = x.shape
+    if dtype == BF16:
+        vecs = torch.empty((n, d), dtype=torch.uint16, device=x.device)
+        scales = None
+    elif dtype == FP8:
+        vecs = torch.empty((n, d), dtype=torch.uint8, device=x.device)
+        scales = torch.empty(n, dtype=torch.float32, device=x.device)
+    else:
+        raise ValueError("dtype must be BF16 or FP8")
+    _check("cng_quantize", lib().cng_quantize(_ptr(x), n, d, dtype, _ptr(vecs), _ptr(scales),
+                                              _stream()))
+    return Store(dtype, vecs, scales)
+
+
+def search_quantized(points: torch.Tensor, store: Store, adj: torch.Tensor, queries: torch.Tensor,
+                     k: int, L: int, entries, visited_log2: int = 0, stats: bool = False):
+    """cng_search_quantized -> (ids, float32-exact dists, hops, ndc)."""
+    x, q = _f32(points), _f32(queries)
+    n, d = x.shape
+    nq = q.shape[0]
+    adj = _ids(adj)
+    if isinstance(entries, int):
+        entries = torch.tensor([entries & 0xFFFFFFFF], dtype=torch.int64).to(torch.int32).to(x.device)
+    entries = _ids(entries)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=x.device)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=x.device)
+    hops = torch.empty(nq, dtype=torch.int32, device=x.device) if stats else None
+    ndc = torch.empty(nq, dtype=torch.int32, device=x.device) if stats else None
+    _check("cng_search_quantized", lib().cng_search_quantized(
+        _ptr(x), _ptr(store.vecs), store.dtype, _ptr(store.scales), n, d, _ptr(adj), adj.shape[1],
+        _ptr(q), nq, k, L, _ptr(entries), entries.numel(), _ptr(ids), _ptr(dists), _ptr(hops),
+        _ptr(ndc), visited_log2, _stream()))
     return ids, dists, hops, ndc
 
 

@@ -292,12 +292,18 @@ cng_status cng_connect(const float *points, int64_t n, int32_t d, uint32_t *adj,
     return ok();
 }
 
-cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t *adj, int32_t W,
-                      const float *queries, int64_t nq, int32_t k, int32_t L,
-                      const uint32_t *entries, int64_t n_entries, uint32_t *ids, float *dists,
-                      uint32_t *hops, uint32_t *ndc, int32_t visited_log2, void *stream)
+static cng_status search_impl(const float *points, const void *vecs, int32_t dtype,
+                              const float *scales, int64_t n, int32_t d, const uint32_t *adj,
+                              int32_t W, const float *queries, int64_t nq, int32_t k, int32_t L,
+                              const uint32_t *entries, int64_t n_entries, uint32_t *ids,
+                              float *dists, uint32_t *hops, uint32_t *ndc, int32_t visited_log2,
+                              void *stream)
 {
     cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (dtype < 0 || dtype > 2) return fail(CNG_EINVAL, "dtype=%d must be 0, 1 or 2", dtype);
+    if (!vecs) return fail(CNG_EINVAL, "vecs is NULL");
+    if (dtype == 2 && !scales) return fail(CNG_EINVAL, "fp8 storage needs scales");
     if (s != CNG_OK) return s;
     if (W < 1) return fail(CNG_EINVAL, "W=%d must be >= 1", W);
     if (W > MAX_W) return fail(CNG_EUNSUPPORTED, "W=%d exceeds %d", W, MAX_W);
@@ -311,6 +317,9 @@ cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t 
     if (!adj || !queries || !entries || !ids || !dists) return fail(CNG_EINVAL, "NULL array argument");
     cng::SearchArgs a{};
     a.points = points;
+    a.vecs = vecs;
+    a.scales = scales;
+    a.store = dtype;
     a.n = n;
     a.d = d;
     a.adj = adj;
@@ -329,6 +338,44 @@ cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t 
     a.vlog2 = visited_log2 ? visited_log2 : cng::search_default_vlog2(Leff);
     hipError_t e = cng::launch_search(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "search");
+    return ok();
+}
+
+cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t *adj, int32_t W,
+                      const float *queries, int64_t nq, int32_t k, int32_t L,
+                      const uint32_t *entries, int64_t n_entries, uint32_t *ids, float *dists,
+                      uint32_t *hops, uint32_t *ndc, int32_t visited_log2, void *stream)
+{
+    return search_impl(points, points, 0, nullptr, n, d, adj, W, queries, nq, k, L, entries,
+                       n_entries, ids, dists, hops, ndc, visited_log2, stream);
+}
+
+cng_status cng_search_quantized(const float *points, const void *vecs, int32_t dtype,
+                                const float *scales, int64_t n, int32_t d, const uint32_t *adj,
+                                int32_t W, const float *queries, int64_t nq, int32_t k, int32_t L,
+                                const uint32_t *entries, int64_t n_entries, uint32_t *ids,
+                                float *dists, uint32_t *hops, uint32_t *ndc, int32_t visited_log2,
+                                void *stream)
+{
+    return search_impl(points, vecs, dtype, scales, n, d, adj, W, queries, nq, k, L, entries,
+                       n_entries, ids, dists, hops, ndc, visited_log2, stream);
+}
+
+size_t cng_quantized_bytes(int64_t n, int32_t d, int32_t dtype)
+{
+    if (n < 0 || d < 1 || dtype < 0 || dtype > 2) return 0;
+    return cng::quantized_bytes(n, d, dtype);
+}
+
+cng_status cng_quantize(const float *points, int64_t n, int32_t d, int32_t dtype, void *vecs,
+                        float *scales, void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (dtype != 1 && dtype != 2) return fail(CNG_EINVAL, "dtype=%d must be 1 (bf16) or 2 (fp8)", dtype);
+    if (!vecs || (dtype == 2 && !scales)) return fail(CNG_EINVAL, "NULL output");
+    hipError_t e = cng::launch_quantize(points, n, d, dtype, vecs, scales, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "quantize");
     return ok();
 }
 

@@ -100,4 +100,112 @@ __device__ __forceinline__ float4 load_chunk(const float *__restrict__ row, int 
     }
 }
 
+
+// ---- reduced-precision element codecs (bit-level; finite inputs)
+// float32 -> bf16 bits, round to nearest even.
+__device__ __forceinline__ uint16_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+// float32 -> OCP E4M3 code, round to nearest even, saturating at +-448.
+__device__ __forceinline__ uint8_t e4m3_encode(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    const uint32_t a = u & 0x7FFFFFFFu;
+    const float af = __uint_as_float(a);
+    if (af >= 448.0f) return (uint8_t)(sign | 0x7Eu);
+    int E = (int)(a >> 23) - 127;
+    if (E < -6) {  // below the smallest normal 2^-6: multiples of 2^-9
+        const float k = __builtin_rintf(af * 512.0f);
+        return (uint8_t)(sign | (uint32_t)k);
+    }
+    uint32_t r = (a & 0x7FFFFFu) + 0x7FFFFu + (((a & 0x7FFFFFu) >> 20) & 1u);
+    if (r & 0x800000u) {  // mantissa rounding carried into the exponent
+        E += 1;
+        r = 0;
+    }
+    const uint32_t mant = (r >> 20) & 7u;
+    if (E > 8 || (E == 8 && mant == 7u)) return (uint8_t)(sign | 0x7Eu);
+    return (uint8_t)(sign | ((uint32_t)(E + 7) << 3) | mant);
+}
+
+// E4M3 code -> float32 value (exact).
+__device__ __forceinline__ float e4m3_value(uint32_t c)
+{
+    const uint32_t e = (c >> 3) & 0xFu, mt = c & 7u;
+    float v = e == 0 ? (float)mt * 0x1p-9f : __uint_as_float(((e + 120u) << 23) | (mt << 20));
+    return (c & 0x80u) ? -v : v;
+}
+
+// Chunk r of lane gl (elements (r*32 + gl)*4 .. +3) of a stored row, as the
+// float32 values it stands for.  ST 0: float32, 1: bf16, 2: fp8 (times scale).
+// VEC: d % 4 == 0 and the row base aligned to one chunk (one vector load).
+template <int ST, bool VEC>
+__device__ __forceinline__ float4 load_stored(const void *__restrict__ base, size_t row, int d, int r,
+                                              int gl, float scale)
+{
+    const int i = (r * 32 + gl) * 4;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ST == 0) {
+        return load_chunk<VEC>(reinterpret_cast<const float *>(base) + row * d, d, r, gl);
+    } else if (ST == 1) {
+        const uint16_t *p = reinterpret_cast<const uint16_t *>(base) + row * d + i;
+        if (VEC) {
+            if (i < d) {
+                const uint2 w = *reinterpret_cast<const uint2 *>(p);
+                v = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                                __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+            }
+        } else {
+            v.x = i + 0 < d ? bf16_value(p[0]) : 0.f;
+            v.y = i + 1 < d ? bf16_value(p[1]) : 0.f;
+            v.z = i + 2 < d ? bf16_value(p[2]) : 0.f;
+            v.w = i + 3 < d ? bf16_value(p[3]) : 0.f;
+        }
+        return v;
+    } else {
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + row * d + i;
+        if (VEC) {
+            if (i < d) {
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+                v = make_float4(e4m3_value(w & 0xFFu) * scale, e4m3_value((w >> 8) & 0xFFu) * scale,
+                                e4m3_value((w >> 16) & 0xFFu) * scale, e4m3_value(w >> 24) * scale);
+            }
+        } else {
+            v.x = i + 0 < d ? e4m3_value(p[0]) * scale : 0.f;
+            v.y = i + 1 < d ? e4m3_value(p[1]) * scale : 0.f;
+            v.z = i + 2 < d ? e4m3_value(p[2]) * scale : 0.f;
+            v.w = i + 3 < d ? e4m3_value(p[3]) * scale : 0.f;
+        }
+        return v;
+    }
+}
+
+// Bitonic sort of n (power of two) 64-bit keys in LDS by one wavefront.
+__device__ inline void wave_sort(uint64_t *k, int n)
+{
+    const int lane = lane_id();
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            wave_sync();
+            for (int t = lane; t < n / 2; t += 64) {
+                int i = 2 * t - (t & (stride - 1));
+                int j = i + stride;
+                bool up = (i & size) == 0;
+                uint64_t a = k[i], b = k[j];
+                if ((a > b) == up) {
+                    k[i] = b;
+                    k[j] = a;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
 }  // namespace cng

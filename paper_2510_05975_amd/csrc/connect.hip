@@ -398,6 +398,9 @@ hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int
             const int64_t cnt = nA - off < BATCH ? nA - off : BATCH;
             SearchArgs sa{};
             sa.points = points;
+            sa.vecs = points;
+            sa.scales = nullptr;
+            sa.store = 0;
             sa.n = n;
             sa.d = d;
             sa.adj = adj;

@@ -8,7 +8,10 @@
 namespace cng {
 
 struct SearchArgs {
-    const float *points;
+    const float *points;       // float32 vectors (queries by id, final re-rank)
+    const void *vecs;          // stored vectors that are scored (== points for float32)
+    const float *scales;       // fp8 per-vector scales (store 2)
+    int store;                 // 0 float32, 1 bf16, 2 fp8-E4M3
     int64_t n;
     int d;
     const uint32_t *adj;
@@ -28,6 +31,11 @@ struct SearchArgs {
 hipError_t launch_search(const SearchArgs &a, hipStream_t stream);
 int search_default_vlog2(int Leff);
 size_t search_lds_per_wave(int Leff, int vlog2);
+
+// reduced-precision storage
+size_t quantized_bytes(int64_t n, int d, int dtype);
+hipError_t launch_quantize(const float *x, int64_t n, int d, int dtype, void *out, float *scales,
+                           hipStream_t stream);
 
 // entry point (centroid rule)
 size_t entry_workspace_bytes(int64_t n, int d);

@@ -54,28 +54,6 @@ __device__ __forceinline__ float float_up(double v)
     return f;
 }
 
-// Bitonic sort of n (power of two) 64-bit keys in LDS by one wavefront.
-__device__ void wave_sort(uint64_t *k, int n)
-{
-    const int lane = lane_id();
-    for (int size = 2; size <= n; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            wave_sync();
-            for (int t = lane; t < n / 2; t += 64) {
-                int i = 2 * t - (t & (stride - 1));
-                int j = i + stride;
-                bool up = (i & size) == 0;
-                uint64_t a = k[i], b = k[j];
-                if ((a > b) == up) {
-                    k[i] = b;
-                    k[j] = a;
-                }
-            }
-        }
-    }
-    wave_sync();
-}
-
 // ---------------------------------------------------------------- prep
 struct PrepOut {
     uint32_t max_norm_bits;  // max |y| over columns (float bits, >= 0)

@@ -16,6 +16,12 @@
 // dwordx4 per lane per 128 dimensions (G lanes per vector, 64/G vectors per
 // instruction, all loads of a batch in flight together) and reduced with a
 // lane butterfly in the fixed order, then merged into the beam by rank.
+//
+// Precision form: the gathered vectors may be stored in bf16 or fp8-E4M3 (one
+// float32 scale per vector).  They are widened to the float32 values they
+// stand for and scored in the same fixed order; when the beam has converged
+// its L entries are re-scored from the float32 vectors and sorted, and the
+// first k are returned (exact float32 distances).
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -85,7 +91,7 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int qcap, int vlog2)
 }
 
 // One query.  G lanes per vector, RND float4 rounds per lane, QS beam slots per lane.
-template <int G, int RND, bool VEC, int QS, int UB>
+template <int G, int RND, bool VEC, int QS, int UB, int ST>
 __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
 {
     constexpr int NG = 64 / G;
@@ -115,10 +121,11 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
         return;
     }
     {
-        const float *row = a.points + (size_t)s0 * d;
+        const float sc0 = ST == 2 ? a.scales[s0] : 1.f;
         float acc = 0.f;
 #pragma unroll
-        for (int r = 0; r < RND; ++r) acc = chunk_fma(load_chunk<VEC>(row, d, r, gl), qr[r], acc);
+        for (int r = 0; r < RND; ++r)
+            acc = chunk_fma(load_stored<ST, VEC>(a.vecs, s0, d, r, gl, sc0), qr[r], acc);
         acc = group_sum<G>(acc);
         if (lane == 0) {
             s.qa[0] = make_key(acc, s0);
@@ -161,9 +168,10 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
                 for (int t = 0; t < UB; ++t) {
                     int c = b + t * NG + grp;
                     if (c < m) {
-                        const float *xr = a.points + (size_t)s.cid[c] * d;
+                        const uint32_t id = s.cid[c];
+                        const float sc = ST == 2 ? a.scales[id] : 1.f;
 #pragma unroll
-                        for (int r = 0; r < RND; ++r) xv[t][r] = load_chunk<VEC>(xr, d, r, gl);
+                        for (int r = 0; r < RND; ++r) xv[t][r] = load_stored<ST, VEC>(a.vecs, id, d, r, gl, sc);
                     } else {
 #pragma unroll
                         for (int r = 0; r < RND; ++r) xv[t][r] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -229,6 +237,31 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
         }
     }
 
+    if (ST != 0) {
+        // ---- re-rank the converged beam with the float32 vectors
+        for (int b0 = 0; b0 < qn; b0 += 64) {
+            const int cnt = qn - b0 < 64 ? qn - b0 : 64;
+            for (int b = 0; b < cnt; b += NG) {
+                const int c = b + grp;
+                float acc = 0.f;
+                if (c < cnt) {
+                    const float *xr = a.points + (size_t)key_id(qa[b0 + c]) * d;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) acc = chunk_fma(load_chunk<VEC>(xr, d, r, gl), qr[r], acc);
+                }
+                acc = group_sum<G>(acc);
+                if (gl == 0 && c < cnt) s.dsc[c] = acc;
+            }
+            wave_sync();
+            if (lane < cnt) qa[b0 + lane] = make_key(s.dsc[lane], key_id(qa[b0 + lane]));
+            wave_sync();
+        }
+        int np = 1;
+        while (np < qn) np <<= 1;
+        for (int e = qn + lane; e < np; e += 64) qa[e] = ~0ull;
+        wave_sort(qa, np);
+    }
+
     // ---- outputs: the first k of the beam
     for (int e = lane; e < a.k; e += 64) {
         uint32_t id = NONE;
@@ -247,7 +280,7 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
     }
 }
 
-template <int G, int RND, bool VEC, int QS, int UB>
+template <int G, int RND, bool VEC, int QS, int UB, int ST>
 __global__ __launch_bounds__(256) void search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -263,35 +296,42 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a)
     s.dsc = reinterpret_cast<float *>(s.tmp + 64);
     s.cid = reinterpret_cast<uint32_t *>(s.dsc + 64);
     s.vis = s.cid + 64;
-    beam_query<G, RND, VEC, QS, UB>(a, qi, s);
+    beam_query<G, RND, VEC, QS, UB, ST>(a, qi, s);
 }
 
 using KernelFn = void (*)(SearchArgs);
 
-template <int G, int RND, bool VEC>
+template <int G, int RND, bool VEC, int ST>
 KernelFn pick_qs(int qs)
 {
     constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : 8;
     switch (qs) {
-    case 1: return search_kernel<G, RND, VEC, 1, UB>;
-    case 2: return search_kernel<G, RND, VEC, 2, UB>;
-    case 4: return search_kernel<G, RND, VEC, 4, UB>;
-    default: return search_kernel<G, RND, VEC, 8, UB>;
+    case 1: return search_kernel<G, RND, VEC, 1, UB, ST>;
+    case 2: return search_kernel<G, RND, VEC, 2, UB, ST>;
+    case 4: return search_kernel<G, RND, VEC, 4, UB, ST>;
+    default: return search_kernel<G, RND, VEC, 8, UB, ST>;
     }
 }
 
-template <bool VEC>
+template <bool VEC, int ST>
 KernelFn pick_kernel(int d, int qs)
 {
-    if (d <= 32) return pick_qs<8, 1, VEC>(qs);
-    if (d <= 64) return pick_qs<16, 1, VEC>(qs);
+    if (d <= 32) return pick_qs<8, 1, VEC, ST>(qs);
+    if (d <= 64) return pick_qs<16, 1, VEC, ST>(qs);
     int rnd = (d + 127) / 128;
-    if (rnd <= 1) return pick_qs<32, 1, VEC>(qs);
-    if (rnd <= 2) return pick_qs<32, 2, VEC>(qs);
-    if (rnd <= 4) return pick_qs<32, 4, VEC>(qs);
-    if (rnd <= 8) return pick_qs<32, 8, VEC>(qs);
-    if (rnd <= 16) return pick_qs<32, 16, VEC>(qs);
-    return pick_qs<32, 32, VEC>(qs);
+    if (rnd <= 1) return pick_qs<32, 1, VEC, ST>(qs);
+    if (rnd <= 2) return pick_qs<32, 2, VEC, ST>(qs);
+    if (rnd <= 4) return pick_qs<32, 4, VEC, ST>(qs);
+    if (rnd <= 8) return pick_qs<32, 8, VEC, ST>(qs);
+    if (rnd <= 16) return pick_qs<32, 16, VEC, ST>(qs);
+    return pick_qs<32, 32, VEC, ST>(qs);
+}
+
+template <bool VEC>
+KernelFn pick_store(int d, int qs, int st)
+{
+    return st == 1 ? pick_kernel<VEC, 1>(d, qs) : st == 2 ? pick_kernel<VEC, 2>(d, qs)
+                                                           : pick_kernel<VEC, 0>(d, qs);
 }
 
 }  // namespace
@@ -313,9 +353,11 @@ hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
 {
     if (a.nq == 0) return hipSuccess;
     const int qs = a.Leff <= 64 ? 1 : a.Leff <= 128 ? 2 : a.Leff <= 256 ? 4 : 8;
+    const size_t vbytes = a.store == 1 ? 8 : a.store == 2 ? 4 : 16;  // one stored chunk
     const bool vec = (a.d % 4 == 0) && ((uintptr_t)a.points % 16 == 0) &&
+                     ((uintptr_t)a.vecs % vbytes == 0) &&
                      (a.query_ids || (uintptr_t)a.queries % 16 == 0);
-    KernelFn fn = vec ? pick_kernel<true>(a.d, qs) : pick_kernel<false>(a.d, qs);
+    KernelFn fn = vec ? pick_store<true>(a.d, qs, a.store) : pick_store<false>(a.d, qs, a.store);
     // the visited table may be shrunk to keep a wave within 64 KB of LDS
     // (it only changes how often a distance is recomputed, never the results)
     SearchArgs b = a;
