@@ -194,6 +194,72 @@ cng_status cng_search_quantized(const float *points, const void *vecs, int32_t d
                                 float *dists, uint32_t *hops, uint32_t *ndc, int32_t visited_log2,
                                 void *stream);
 
+/* ------------------------------------------------------------------ learned entry point */
+/* Not in the paper, which starts every search at one navigating node (the
+ * point nearest the centroid, Algorithm 3).  A multilayer perceptron
+ * d -> H -> H -> K (ReLU hidden layers) scores K entry nodes for a query; the
+ * navigating node remains the fallback when the top softmax probability is
+ * below a threshold.  Parameters: one float32 vector, in this order:
+ * W1 [d x H], b1 [H], W2 [H x H], b2 [H], W3 [H x K], b3 [K] (row-major,
+ * y = x W + b).  precision 0: float32 matrix-core products; 1: bf16 inputs,
+ * float32 accumulation. */
+
+/* k-means (Lloyd) over points: centres start at points[init_ids[j]]
+ * (init_ids [K], device), `iters` rounds of assignment (nearest centre by
+ * (D, index)) and mean update (float atomics: not bit-reproducible).
+ * entries [K] = point nearest each final centre.  Synchronises `stream`. */
+size_t cng_kmeans_workspace_size(int64_t n, int32_t d, int32_t K);
+cng_status cng_kmeans(const float *points, int64_t n, int32_t d, int32_t K, int32_t iters,
+                      const uint32_t *init_ids, float *centers, uint32_t *entries, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* Training labels from the plain search itself: for each query, the best
+ * point of a float32 beam search (beam L, from the navigating node `nav`)
+ * and then the index (0..K-1) of the entry node nearest to that point.
+ * labels [nq] uint32.  Synchronises `stream`. */
+cng_status cng_entry_labels_workspace_size(int64_t n, int32_t d, int64_t nq, int32_t K,
+                                           size_t *bytes_host);
+cng_status cng_entry_labels(const float *points, int64_t n, int32_t d, const uint32_t *adj, int32_t W,
+                            uint32_t nav, const float *queries, int64_t nq, int32_t L,
+                            const uint32_t *entries, int32_t K, uint32_t *labels, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* Number of parameters and workspace bytes for batch B. */
+int64_t cng_mlp_param_count(int32_t d, int32_t H, int32_t K);
+size_t cng_mlp_workspace_size(int32_t d, int32_t H, int32_t K, int32_t B);
+
+/* Softmax cross-entropy gradients of a batch: rows batch_ids[0..B) of X
+ * [* x d] (batch_ids may be NULL: rows 0..B-1) with labels[row] in [0, K).
+ * grads [param_count]; loss (device float, may be NULL) = mean loss. */
+cng_status cng_mlp_gradients(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
+                             const uint32_t *labels, const uint32_t *batch_ids, int32_t B,
+                             int32_t precision, float *grads, float *loss, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on params with moments m1, m2. */
+cng_status cng_mlp_adam(float *params, const float *grads, float *m1, float *m2, int32_t d,
+                        int32_t H, int32_t K, int32_t step, float lr, float beta1, float beta2,
+                        float eps, void *stream);
+
+/* Scores: logits [B x K] for X [B x d]. */
+cng_status cng_mlp_logits(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
+                          int32_t B, int32_t precision, float *logits, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* Entry choice per query: entries[argmax] (ties to the lower index) if its
+ * softmax probability is >= theta, else `fallback`.  out_entry [B] uint32,
+ * out_conf [B] float (may be NULL). */
+cng_status cng_entry_predict(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
+                             int32_t B, int32_t precision, const uint32_t *entries,
+                             uint32_t fallback, float theta, uint32_t *out_entry, float *out_conf,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
+/* Ablation baseline without a network: entries[index of the nearest centre]. */
+size_t cng_nearest_centre_workspace_size(int64_t nq, int32_t d, int32_t K);
+cng_status cng_nearest_centre_entry(const float *queries, int64_t nq, int32_t d, const float *centers,
+                                    int32_t K, const uint32_t *entries, uint32_t *out_entry,
+                                    void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Message of the last non-OK status on the calling thread ("" if none). */

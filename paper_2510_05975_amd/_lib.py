@@ -73,6 +73,21 @@ _SIGS = {
     "cng_quantize": (C.c_int, [vp, i64, i32, i32, vp, vp, vp]),
     "cng_search_quantized": (C.c_int, [vp, vp, i32, vp, i64, i32, vp, i32, vp, i64, i32, i32, vp,
                                        i64, vp, vp, vp, vp, i32, vp]),
+    "cng_kmeans_workspace_size": (sz, [i64, i32, i32]),
+    "cng_kmeans": (C.c_int, [vp, i64, i32, i32, i32, vp, vp, vp, vp, sz, vp]),
+    "cng_entry_labels_workspace_size": (C.c_int, [i64, i32, i64, i32, C.POINTER(sz)]),
+    "cng_entry_labels": (C.c_int, [vp, i64, i32, vp, i32, u32, vp, i64, i32, vp, i32, vp, vp, sz,
+                                   vp]),
+    "cng_mlp_param_count": (i64, [i32, i32, i32]),
+    "cng_mlp_workspace_size": (sz, [i32, i32, i32, i32]),
+    "cng_mlp_gradients": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, sz, vp]),
+    "cng_mlp_adam": (C.c_int, [vp, vp, vp, vp, i32, i32, i32, i32, C.c_float, C.c_float, C.c_float,
+                               C.c_float, vp]),
+    "cng_mlp_logits": (C.c_int, [vp, i32, i32, i32, vp, i32, i32, vp, vp, sz, vp]),
+    "cng_entry_predict": (C.c_int, [vp, i32, i32, i32, vp, i32, i32, vp, u32, C.c_float, vp, vp,
+                                    vp, sz, vp]),
+    "cng_nearest_centre_workspace_size": (sz, [i64, i32, i32]),
+    "cng_nearest_centre_entry": (C.c_int, [vp, i64, i32, vp, i32, vp, vp, vp, sz, vp]),
 }
 
 
@@ -288,6 +303,95 @@ def search_quantized(points: torch.Tensor, store: Store, adj: torch.Tensor, quer
         _ptr(q), nq, k, L, _ptr(entries), entries.numel(), _ptr(ids), _ptr(dists), _ptr(hops),
         _ptr(ndc), visited_log2, _stream()))
     return ids, dists, hops, ndc
+
+
+# ---------------------------------------------------------------- learned entry point
+def kmeans(points: torch.Tensor, K: int, iters: int, init_ids: torch.Tensor):
+    """cng_kmeans -> (centers [K, d] float32, entries [K] int32)."""
+    x = _f32(points)
+    n, d = x.shape
+    nb = lib().cng_kmeans_workspace_size(n, d, K)
+    ws = _ws(nb, x.device)
+    centers = torch.empty((K, d), dtype=torch.float32, device=x.device)
+    entries = torch.empty(K, dtype=torch.int32, device=x.device)
+    _check("cng_kmeans", lib().cng_kmeans(_ptr(x), n, d, K, iters, _ptr(_ids(init_ids)),
+                                          _ptr(centers), _ptr(entries), _ptr(ws), nb, _stream()))
+    return centers, entries
+
+
+def entry_labels(points, adj, nav: int, queries, L: int, entries):
+    x, q = _f32(points), _f32(queries)
+    n, d = x.shape
+    nq = q.shape[0]
+    K = entries.numel()
+    nb = sz(0)
+    _check("cng_entry_labels_workspace_size",
+           lib().cng_entry_labels_workspace_size(n, d, nq, K, C.byref(nb)))
+    ws = _ws(nb.value, x.device)
+    labels = torch.empty(nq, dtype=torch.int32, device=x.device)
+    adj = _ids(adj)
+    _check("cng_entry_labels", lib().cng_entry_labels(_ptr(x), n, d, _ptr(adj), adj.shape[1], nav,
+                                                      _ptr(q), nq, L, _ptr(_ids(entries)), K,
+                                                      _ptr(labels), _ptr(ws), nb.value, _stream()))
+    return labels
+
+
+def mlp_param_count(d: int, H: int, K: int) -> int:
+    return int(lib().cng_mlp_param_count(d, H, K))
+
+
+def mlp_gradients(params, d, H, K, X, labels, batch_ids, B, precision, grads, loss=None, ws=None):
+    X = _f32(X)
+    nb = lib().cng_mlp_workspace_size(d, H, K, B)
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, X.device)
+    _check("cng_mlp_gradients", lib().cng_mlp_gradients(
+        _ptr(params), d, H, K, _ptr(X), _ptr(_ids(labels)),
+        _ptr(batch_ids) if batch_ids is not None else None, B, precision, _ptr(grads),
+        _ptr(loss), _ptr(ws), ws.numel(), _stream()))
+    return ws
+
+
+def mlp_adam(params, grads, m1, m2, d, H, K, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check("cng_mlp_adam", lib().cng_mlp_adam(_ptr(params), _ptr(grads), _ptr(m1), _ptr(m2), d, H,
+                                              K, step, lr, beta1, beta2, eps, _stream()))
+
+
+def mlp_logits(params, d, H, K, X, precision):
+    X = _f32(X)
+    B = X.shape[0]
+    nb = lib().cng_mlp_workspace_size(d, H, K, B)
+    ws = _ws(nb, X.device)
+    Z = torch.empty((B, K), dtype=torch.float32, device=X.device)
+    _check("cng_mlp_logits", lib().cng_mlp_logits(_ptr(params), d, H, K, _ptr(X), B, precision,
+                                                  _ptr(Z), _ptr(ws), nb, _stream()))
+    return Z
+
+
+def entry_predict(params, d, H, K, X, precision, entries, fallback: int, theta: float):
+    X = _f32(X)
+    B = X.shape[0]
+    nb = lib().cng_mlp_workspace_size(d, H, K, B)
+    ws = _ws(nb, X.device)
+    out = torch.empty(B, dtype=torch.int32, device=X.device)
+    conf = torch.empty(B, dtype=torch.float32, device=X.device)
+    _check("cng_entry_predict", lib().cng_entry_predict(_ptr(params), d, H, K, _ptr(X), B, precision,
+                                                        _ptr(_ids(entries)), fallback, theta,
+                                                        _ptr(out), _ptr(conf), _ptr(ws), nb,
+                                                        _stream()))
+    return out, conf
+
+
+def nearest_centre_entry(queries, centers, entries):
+    q, c = _f32(queries), _f32(centers)
+    nq, d = q.shape
+    K = c.shape[0]
+    nb = lib().cng_nearest_centre_workspace_size(nq, d, K)
+    ws = _ws(nb, q.device)
+    out = torch.empty(nq, dtype=torch.int32, device=q.device)
+    _check("cng_nearest_centre_entry", lib().cng_nearest_centre_entry(
+        _ptr(q), nq, d, _ptr(c), K, _ptr(_ids(entries)), _ptr(out), _ptr(ws), nb, _stream()))
+    return out
 
 
 def u32(t: torch.Tensor):

@@ -379,4 +379,202 @@ cng_status cng_quantize(const float *points, int64_t n, int32_t d, int32_t dtype
     return ok();
 }
 
+// ---------------------------------------------------------------- learned entry point
+
+size_t cng_kmeans_workspace_size(int64_t n, int32_t d, int32_t K)
+{
+    if (n < 1 || d < 1 || K < 1) return 0;
+    return cng::kmeans_workspace_bytes(n, d, K);
+}
+
+cng_status cng_kmeans(const float *points, int64_t n, int32_t d, int32_t K, int32_t iters,
+                      const uint32_t *init_ids, float *centers, uint32_t *entries, void *workspace,
+                      size_t ws_bytes, void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (K < 1 || K > n) return fail(CNG_EINVAL, "K=%d must be in [1, n]", K);
+    if (iters < 0) return fail(CNG_EINVAL, "iters must be >= 0");
+    if (!init_ids || !centers || !entries) return fail(CNG_EINVAL, "NULL array argument");
+    if (!workspace || ws_bytes < cng::kmeans_workspace_bytes(n, d, K))
+        return fail(CNG_ENOMEM, "workspace too small");
+    hipError_t e = cng::run_kmeans(points, n, d, K, iters, init_ids, centers, entries, workspace,
+                                   (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "kmeans");
+    return ok();
+}
+
+static cng_status check_mlp(int32_t d, int32_t H, int32_t K, int32_t B, int32_t precision)
+{
+    if (d < 1 || d > 4096 || H < 1 || H > 8192 || K < 1 || K > 65536)
+        return fail(CNG_EINVAL, "MLP shape d=%d H=%d K=%d out of range", d, H, K);
+    if (B < 1) return fail(CNG_EINVAL, "batch B=%d must be >= 1", B);
+    if (precision != 0 && precision != 1) return fail(CNG_EINVAL, "precision must be 0 (fp32) or 1 (bf16)");
+    return CNG_OK;
+}
+
+int64_t cng_mlp_param_count(int32_t d, int32_t H, int32_t K)
+{
+    if (d < 1 || H < 1 || K < 1) return 0;
+    return cng::MlpShape(d, H, K).total;
+}
+
+size_t cng_mlp_workspace_size(int32_t d, int32_t H, int32_t K, int32_t B)
+{
+    if (d < 1 || H < 1 || K < 1 || B < 1) return 0;
+    return cng::mlp_workspace_floats(cng::MlpShape(d, H, K), B) * 4;
+}
+
+cng_status cng_mlp_gradients(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
+                             const uint32_t *labels, const uint32_t *batch_ids, int32_t B,
+                             int32_t precision, float *grads, float *loss, void *workspace,
+                             size_t ws_bytes, void *stream)
+{
+    cng_status s = check_mlp(d, H, K, B, precision);
+    if (s != CNG_OK) return s;
+    if (!params || !X || !labels || !grads) return fail(CNG_EINVAL, "NULL array argument");
+    cng::MlpShape sh(d, H, K);
+    if (!workspace || ws_bytes < cng::mlp_workspace_floats(sh, B) * 4) return fail(CNG_ENOMEM, "workspace too small");
+    hipError_t e = cng::mlp_gradients(sh, params, X, labels, batch_ids, B, precision == 1,
+                                      (float *)workspace, grads, loss, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp gradients");
+    return ok();
+}
+
+cng_status cng_mlp_adam(float *params, const float *grads, float *m1, float *m2, int32_t d,
+                        int32_t H, int32_t K, int32_t step, float lr, float beta1, float beta2,
+                        float eps, void *stream)
+{
+    cng_status s = check_mlp(d, H, K, 1, 0);
+    if (s != CNG_OK) return s;
+    if (!params || !grads || !m1 || !m2) return fail(CNG_EINVAL, "NULL array argument");
+    if (step < 1) return fail(CNG_EINVAL, "step must be >= 1");
+    hipError_t e = cng::mlp_adam(cng::MlpShape(d, H, K), params, grads, m1, m2, step, lr, beta1,
+                                 beta2, eps, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp adam");
+    return ok();
+}
+
+cng_status cng_mlp_logits(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
+                          int32_t B, int32_t precision, float *logits, void *workspace,
+                          size_t ws_bytes, void *stream)
+{
+    cng_status s = check_mlp(d, H, K, B, precision);
+    if (s != CNG_OK) return s;
+    if (!params || !X || !logits) return fail(CNG_EINVAL, "NULL array argument");
+    cng::MlpShape sh(d, H, K);
+    if (!workspace || ws_bytes < cng::mlp_workspace_floats(sh, B) * 4) return fail(CNG_ENOMEM, "workspace too small");
+    hipError_t e = cng::mlp_forward(sh, params, X, nullptr, B, precision == 1, (float *)workspace,
+                                    logits, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp logits");
+    return ok();
+}
+
+cng_status cng_entry_predict(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
+                             int32_t B, int32_t precision, const uint32_t *entries,
+                             uint32_t fallback, float theta, uint32_t *out_entry, float *out_conf,
+                             void *workspace, size_t ws_bytes, void *stream)
+{
+    cng_status s = check_mlp(d, H, K, B, precision);
+    if (s != CNG_OK) return s;
+    if (!params || !X || !entries || !out_entry) return fail(CNG_EINVAL, "NULL array argument");
+    cng::MlpShape sh(d, H, K);
+    if (!workspace || ws_bytes < cng::mlp_workspace_floats(sh, B) * 4) return fail(CNG_ENOMEM, "workspace too small");
+    hipError_t e = cng::mlp_predict(sh, params, X, B, precision == 1, entries, fallback, theta,
+                                    (float *)workspace, out_entry, out_conf, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "entry predict");
+    return ok();
+}
+
+cng_status cng_entry_labels_workspace_size(int64_t n, int32_t d, int64_t nq, int32_t K,
+                                           size_t *bytes)
+{
+    if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
+    if (n < 1 || d < 1 || nq < 0 || K < 1) return fail(CNG_EINVAL, "sizes out of range");
+    cng::KnnPlan p = cng::knn_plan(nq, K, d, 1, 0);
+    *bytes = align256(p.bytes) + align256((size_t)nq * d * 4) + align256((size_t)K * d * 4) +
+             align256((size_t)nq * 4) * 3;
+    return ok();
+}
+
+cng_status cng_entry_labels(const float *points, int64_t n, int32_t d, const uint32_t *adj, int32_t W,
+                            uint32_t nav, const float *queries, int64_t nq, int32_t L,
+                            const uint32_t *entries, int32_t K, uint32_t *labels, void *workspace,
+                            size_t ws_bytes, void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    size_t need = 0;
+    s = cng_entry_labels_workspace_size(n, d, nq, K, &need);
+    if (s != CNG_OK) return s;
+    if (!adj || !queries || !entries || !labels) return fail(CNG_EINVAL, "NULL array argument");
+    if ((int64_t)nav >= n) return fail(CNG_EINVAL, "navigating node %u >= n", nav);
+    if (L < 1 || L > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "L out of range");
+    if (W < 1 || W > MAX_W) return fail(CNG_EUNSUPPORTED, "W out of range");
+    if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace too small");
+    if (nq == 0) return ok();
+    hipStream_t st = (hipStream_t)stream;
+    cng::KnnPlan p = cng::knn_plan(nq, K, d, 1, 0);
+    unsigned char *w = (unsigned char *)workspace;
+    void *kws = w;
+    w += align256(p.bytes);
+    float *found = (float *)w;
+    w += align256((size_t)nq * d * 4);
+    float *evec = (float *)w;
+    w += align256((size_t)K * d * 4);
+    uint32_t *top = (uint32_t *)w;
+    w += align256((size_t)nq * 4);
+    float *topd = (float *)w;
+    w += align256((size_t)nq * 4);
+    uint32_t *nav_dev = (uint32_t *)w;
+    hipError_t e = hipMemcpyAsync(nav_dev, &nav, 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "labels");
+    // 1. plain float32 search from the navigating node: the best point found
+    cng::SearchArgs a{};
+    a.points = points; a.vecs = points; a.scales = nullptr; a.store = 0;
+    a.n = n; a.d = d; a.adj = adj; a.W = W; a.queries = queries; a.query_ids = nullptr; a.nq = nq;
+    a.k = 1; a.Leff = L; a.entries = nav_dev; a.per_query_entry = 0;
+    a.ids = top; a.dists = topd; a.hops = nullptr; a.ndc = nullptr;
+    a.vlog2 = cng::search_default_vlog2(L);
+    e = cng::launch_search(a, st);
+    // 2. label = entry node nearest to that point, by (D, index)
+    if (e == hipSuccess) e = cng::gather_points(points, d, top, nq, found, st);
+    if (e == hipSuccess) e = cng::gather_points(points, d, entries, K, evec, st);
+    if (e == hipSuccess)
+        e = cng::launch_knn(found, nq, evec, K, d, 1, 0, p, labels, topd, kws, st, nullptr, nullptr, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "labels");
+    return ok();
+}
+
+cng_status cng_nearest_centre_entry(const float *queries, int64_t nq, int32_t d, const float *centers,
+                                    int32_t K, const uint32_t *entries, uint32_t *out_entry,
+                                    void *workspace, size_t ws_bytes, void *stream)
+{
+    if (nq < 0 || d < 1 || K < 1) return fail(CNG_EINVAL, "sizes out of range");
+    if (!queries || !centers || !entries || !out_entry) return fail(CNG_EINVAL, "NULL array argument");
+    cng::KnnPlan p = cng::knn_plan(nq, K, d, 1, 0);
+    const size_t need = align256(p.bytes) + align256((size_t)nq * 4) * 2;
+    if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace of %zu bytes < %zu", ws_bytes, need);
+    if (nq == 0) return ok();
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)workspace;
+    uint32_t *j = (uint32_t *)(w + align256(p.bytes));
+    float *jd = (float *)(w + align256(p.bytes) + align256((size_t)nq * 4));
+    hipError_t e = cng::launch_knn(queries, nq, centers, K, d, 1, 0, p, j, jd, w, st, nullptr, nullptr, nullptr);
+    if (e == hipSuccess) e = cng::map_through(j, nq, entries, out_entry, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "nearest centre");
+    return ok();
+}
+
+size_t cng_nearest_centre_workspace_size(int64_t nq, int32_t d, int32_t K)
+{
+    if (nq < 0 || d < 1 || K < 1) return 0;
+    cng::KnnPlan p = cng::knn_plan(nq, K, d, 1, 0);
+    return align256(p.bytes) + align256((size_t)nq * 4) * 2;
+}
+
 }  // extern "C"

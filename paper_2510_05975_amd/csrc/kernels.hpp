@@ -64,4 +64,33 @@ hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int
                        uint32_t entry_host, int Lc, int vlog2, void *ws, hipStream_t stream,
                        int64_t *rounds, int64_t *added, int *capacity_error);
 
+// learned entry point: MLP d -> H -> H -> K
+struct MlpShape {
+    int d, H, K;
+    int64_t oW1, ob1, oW2, ob2, oW3, ob3, total;  // offsets into the parameter vector
+    MlpShape(int d_, int H_, int K_);
+};
+size_t mlp_workspace_floats(const MlpShape &s, int B);
+hipError_t mlp_forward(const MlpShape &s, const float *P, const float *X, const uint32_t *idx, int B,
+                       bool bf16, float *ws, float *Z_out, hipStream_t st);
+hipError_t mlp_gradients(const MlpShape &s, const float *P, const float *X, const uint32_t *lab,
+                         const uint32_t *idx, int B, bool bf16, float *ws, float *G,
+                         float *loss_mean, hipStream_t st);
+hipError_t mlp_adam(const MlpShape &s, float *P, const float *G, float *M1, float *M2, int step,
+                    float lr, float b1, float b2, float eps, hipStream_t st);
+hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B, bool bf16,
+                       const uint32_t *entries, uint32_t fallback, float theta, float *ws,
+                       uint32_t *out, float *conf, hipStream_t st);
+
+// k-means (entry nodes of the learned entry point)
+size_t kmeans_workspace_bytes(int64_t n, int d, int K);
+hipError_t run_kmeans(const float *points, int64_t n, int d, int K, int iters,
+                      const uint32_t *init_ids, float *centers, uint32_t *entries, void *ws,
+                      hipStream_t st);
+
+hipError_t gather_points(const float *x, int d, const uint32_t *ids, int64_t m, float *out,
+                         hipStream_t st);
+hipError_t map_through(const uint32_t *idx, int64_t m, const uint32_t *table, uint32_t *out,
+                       hipStream_t st);
+
 }  // namespace cng

@@ -1,0 +1,299 @@
+// Learned entry point: a multilayer perceptron d -> H -> H -> K (ReLU) maps a
+// query to scores over K graph entry nodes; softmax cross-entropy against the
+// entry that the plain search itself found best; Adam updates.  Not part of
+// the paper (which starts every search at one navigating node, Algorithm 3);
+// the navigating node stays the fallback when the network is not confident.
+//
+// Every matrix product runs on the matrix cores, one wavefront per 32 x 32
+// output tile: bf16 inputs (v_mfma_f32_32x32x16_bf16) or float32 inputs
+// (v_mfma_f32_32x32x2f32, used for gradient checks), float32 accumulation.
+// Operands are read through strides, so transposed products need no copies.
+// Parameters, gradients and Adam moments are float32.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cng {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct GemmArgs {
+    int M, N, K;
+    const float *A;
+    int64_t as0, as1;  // A(i, k) = A[ri(i) * as0 + rk(k) * as1]
+    const uint32_t *ri, *rk;  // optional index maps of A's first / second index
+    const float *B;
+    int64_t bs0, bs1;  // B(k, j) = B[k * bs0 + j * bs1]
+    float *C;          // C[i * N + j]
+    const float *bias; // optional, per column
+    const float *mask; // optional: C(i, j) *= (mask[i * N + j] > 0)
+    int relu;
+};
+
+__device__ __forceinline__ __bf16 to_bf16(float f)
+{
+    uint16_t b = bf16_bits(f);
+    return __builtin_bit_cast(__bf16, b);
+}
+
+__device__ __forceinline__ int64_t aidx(const GemmArgs &g, int i, int k)
+{
+    const int64_t ii = g.ri ? (int64_t)g.ri[i] : i, kk = g.rk ? (int64_t)g.rk[k] : k;
+    return ii * g.as0 + kk * g.as1;
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g)
+{
+    const int lane = lane_id();
+    const int tilesN = (g.N + 31) / 32;
+    const int ti = blockIdx.x / tilesN, tj = blockIdx.x % tilesN;
+    const int i0 = ti * 32, j0 = tj * 32;
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int ia = i0 + (lane & 31), jb = j0 + (lane & 31);
+    const bool iok = ia < g.M, jok = jb < g.N;
+    if (BF16) {
+        for (int k0 = 0; k0 < g.K; k0 += 16) {
+            bf16x8 av, bv;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = k0 + (lane >> 5) * 8 + t;
+                const bool kok = k < g.K;
+                av[t] = to_bf16(iok && kok ? g.A[aidx(g, ia, k)] : 0.f);
+                bv[t] = to_bf16(jok && kok ? g.B[k * g.bs0 + jb * g.bs1] : 0.f);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    } else {
+        for (int k0 = 0; k0 < g.K; k0 += 2) {
+            const int k = k0 + (lane >> 5);
+            const bool kok = k < g.K;
+            const float av = iok && kok ? g.A[aidx(g, ia, k)] : 0.f;
+            const float bv = jok && kok ? g.B[k * g.bs0 + jb * g.bs1] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + (lane & 31);
+        if (i < g.M && j < g.N) {
+            float v = acc[r];
+            if (g.bias) v = v + g.bias[j];
+            if (g.relu) v = v > 0.f ? v : 0.f;
+            if (g.mask && !(g.mask[(int64_t)i * g.N + j] > 0.f)) v = 0.f;
+            g.C[(int64_t)i * g.N + j] = v;
+        }
+    }
+}
+
+hipError_t gemm(const GemmArgs &g, bool bf16, hipStream_t st)
+{
+    const unsigned tiles = (unsigned)(((g.M + 31) / 32) * ((g.N + 31) / 32));
+    if (bf16) hipLaunchKernelGGL(gemm_kernel<true>, dim3(tiles), dim3(64), 0, st, g);
+    else hipLaunchKernelGGL(gemm_kernel<false>, dim3(tiles), dim3(64), 0, st, g);
+    return hipGetLastError();
+}
+
+// Softmax cross-entropy per row (one wavefront per row): loss[i] and
+// dZ = (softmax(Z) - onehot(label)) / B.
+__global__ __launch_bounds__(256) void softmax_xent(const float *__restrict__ Z, const uint32_t *__restrict__ lab,
+                                                    const uint32_t *__restrict__ idx, int B, int K,
+                                                    float *__restrict__ dZ, float *__restrict__ loss)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (i >= B) return;
+    const float *z = Z + i * K;
+    float m = -__builtin_inff();
+    for (int j = lane; j < K; j += 64) m = __builtin_fmaxf(m, z[j]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, off, 64));
+    float s = 0.f;
+    for (int j = lane; j < K; j += 64) s += expf(z[j] - m);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    const uint32_t y = lab[idx ? idx[i] : i];  // a label >= K contributes no target
+    const float inv = 1.f / s;
+    for (int j = lane; j < K; j += 64) {
+        const float p = expf(z[j] - m) * inv;
+        dZ[i * K + j] = (p - (j == (int)y ? 1.f : 0.f)) / (float)B;
+    }
+    if (lane == 0) loss[i] = y < (uint32_t)K ? (m + logf(s)) - z[y] : 0.f;
+}
+
+// Column sums (bias gradients), one thread per column, rows in order.
+__global__ void colsum(const float *__restrict__ X, int B, int N, float *__restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int i = 0; i < B; ++i) s += X[(int64_t)i * N + j];
+    out[j] = s;
+}
+
+__global__ void mean_of(const float *__restrict__ x, int n, float *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += x[i];
+    *out = (float)(s / n);
+}
+
+__global__ void adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                     float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                     float c1, float c2)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float gt = g[t];
+    const float mt = b1 * m[t] + (1.f - b1) * gt;
+    const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    w[t] = w[t] - lr * (mt / c1) / (__builtin_sqrtf(vt / c2) + eps);
+}
+
+// Entry choice: argmax of the scores (ties to the lower index) and its softmax
+// probability; below theta the navigating node is used instead.
+__global__ __launch_bounds__(256) void predict_entry(const float *__restrict__ Z, int B, int K,
+                                                     const uint32_t *__restrict__ entries,
+                                                     uint32_t fallback, float theta,
+                                                     uint32_t *__restrict__ out,
+                                                     float *__restrict__ conf)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (i >= B) return;
+    const float *z = Z + i * K;
+    float m = -__builtin_inff();
+    int am = 0x7FFFFFFF;
+    for (int j = lane; j < K; j += 64)
+        if (z[j] > m) {
+            m = z[j];
+            am = j;
+        }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float om = __shfl_xor(m, off, 64);
+        const int oa = __shfl_xor(am, off, 64);
+        if (om > m || (om == m && oa < am)) {
+            m = om;
+            am = oa;
+        }
+    }
+    float s = 0.f;
+    for (int j = lane; j < K; j += 64) s += expf(z[j] - m);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        const float p = 1.f / s;
+        if (conf) conf[i] = p;
+        out[i] = (am < K && p >= theta) ? entries[am] : fallback;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+MlpShape::MlpShape(int d_, int H_, int K_) : d(d_), H(H_), K(K_)
+{
+    oW1 = 0;
+    ob1 = oW1 + (int64_t)d * H;
+    oW2 = ob1 + H;
+    ob2 = oW2 + (int64_t)H * H;
+    oW3 = ob2 + H;
+    ob3 = oW3 + (int64_t)H * K;
+    total = ob3 + K;
+}
+
+size_t mlp_workspace_floats(const MlpShape &s, int B)
+{
+    // H1, H2, Z, dZ, dH2, dH1, loss
+    return (size_t)B * s.H * 4 + (size_t)B * s.K * 2 + (size_t)B + 64;
+}
+
+static GemmArgs mk(int M, int N, int K, const float *A, int64_t as0, int64_t as1, const float *B,
+                   int64_t bs0, int64_t bs1, float *C, const float *bias, const float *mask, int relu,
+                   const uint32_t *ri = nullptr, const uint32_t *rk = nullptr)
+{
+    GemmArgs g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.as0 = as0; g.as1 = as1; g.ri = ri; g.rk = rk;
+    g.B = B; g.bs0 = bs0; g.bs1 = bs1;
+    g.C = C; g.bias = bias; g.mask = mask; g.relu = relu;
+    return g;
+}
+
+hipError_t mlp_forward(const MlpShape &s, const float *P, const float *X, const uint32_t *idx, int B,
+                       bool bf16, float *ws, float *Z_out, hipStream_t st)
+{
+    float *H1 = ws, *H2 = H1 + (size_t)B * s.H;
+    float *Z = Z_out ? Z_out : H2 + (size_t)B * s.H * 3;
+    hipError_t e;
+    e = gemm(mk(B, s.H, s.d, X, s.d, 1, P + s.oW1, s.H, 1, H1, P + s.ob1, nullptr, 1, idx), bf16, st);
+    if (e != hipSuccess) return e;
+    e = gemm(mk(B, s.H, s.H, H1, s.H, 1, P + s.oW2, s.H, 1, H2, P + s.ob2, nullptr, 1), bf16, st);
+    if (e != hipSuccess) return e;
+    return gemm(mk(B, s.K, s.H, H2, s.H, 1, P + s.oW3, s.K, 1, Z, P + s.ob3, nullptr, 0), bf16, st);
+}
+
+hipError_t mlp_gradients(const MlpShape &s, const float *P, const float *X, const uint32_t *lab,
+                         const uint32_t *idx, int B, bool bf16, float *ws, float *G,
+                         float *loss_mean, hipStream_t st)
+{
+    float *H1 = ws, *H2 = H1 + (size_t)B * s.H;
+    float *dH2 = H2 + (size_t)B * s.H, *dH1 = dH2 + (size_t)B * s.H;
+    float *Z = dH1 + (size_t)B * s.H, *dZ = Z + (size_t)B * s.K, *loss = dZ + (size_t)B * s.K;
+    hipError_t e = mlp_forward(s, P, X, idx, B, bf16, ws, Z, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(softmax_xent, dim3((B + 3) / 4), dim3(256), 0, st, Z, lab, idx, B, s.K, dZ, loss);
+    if (loss_mean) hipLaunchKernelGGL(mean_of, dim3(1), dim3(1), 0, st, loss, B, loss_mean);
+    // layer 3: dW3 = H2^T dZ, db3 = colsum dZ, dH2 = (dZ W3^T) * (H2 > 0)
+    e = gemm(mk(s.H, s.K, B, H2, 1, s.H, dZ, s.K, 1, G + s.oW3, nullptr, nullptr, 0), bf16, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum, dim3((s.K + 255) / 256), dim3(256), 0, st, dZ, B, s.K, G + s.ob3);
+    e = gemm(mk(B, s.H, s.K, dZ, s.K, 1, P + s.oW3, 1, s.K, dH2, nullptr, H2, 0), bf16, st);
+    if (e != hipSuccess) return e;
+    // layer 2
+    e = gemm(mk(s.H, s.H, B, H1, 1, s.H, dH2, s.H, 1, G + s.oW2, nullptr, nullptr, 0), bf16, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum, dim3((s.H + 255) / 256), dim3(256), 0, st, dH2, B, s.H, G + s.ob2);
+    e = gemm(mk(B, s.H, s.H, dH2, s.H, 1, P + s.oW2, 1, s.H, dH1, nullptr, H1, 0), bf16, st);
+    if (e != hipSuccess) return e;
+    // layer 1
+    e = gemm(mk(s.d, s.H, B, X, 1, s.d, dH1, s.H, 1, G + s.oW1, nullptr, nullptr, 0, nullptr, idx),
+             bf16, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum, dim3((s.H + 255) / 256), dim3(256), 0, st, dH1, B, s.H, G + s.ob1);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(const MlpShape &s, float *P, const float *G, float *M1, float *M2, int step,
+                    float lr, float b1, float b2, float eps, hipStream_t st)
+{
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam, dim3((unsigned)((s.total + 255) / 256)), dim3(256), 0, st, P, G, M1, M2,
+                       s.total, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B, bool bf16,
+                       const uint32_t *entries, uint32_t fallback, float theta, float *ws,
+                       uint32_t *out, float *conf, hipStream_t st)
+{
+    float *Z = ws + (size_t)B * s.H * 2;
+    hipError_t e = mlp_forward(s, P, X, nullptr, B, bf16, ws, Z, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(predict_entry, dim3((B + 3) / 4), dim3(256), 0, st, Z, B, s.K, entries,
+                       fallback, theta, out, conf);
+    return hipGetLastError();
+}
+
+}  // namespace cng

@@ -174,3 +174,37 @@ def uniform_cube(n: int, nq: int, d: int, seed: int = 0, scale: float = 1.0):
     g = _rng(seed)
     return ((g.random((n, d)) * scale).astype(np.float32),
             (g.random((nq, d)) * scale).astype(np.float32))
+
+
+def fresh_queries(cfg: int, nq: int, stream: int, seed: int = 0):
+    """nq new queries from the same distribution as standard case ``cfg`` (the
+    same centres / latent map, drawn first from ``seed``), sampled from an
+    independent generator keyed by (seed, stream) -- e.g. training queries that
+    share no draws with the base set or the evaluation queries."""
+    c = CONFIGS[cfg]
+    gname, d = c["gen"], c["d"]
+    qg = _rng(1_000_003 * (seed + 1) + stream)
+    if gname == "vmf":
+        return vmf(0, nq, seed=seed, d=d, query_seed=1_000_003 * (seed + 1) + stream)[1]
+    g = _rng(seed)
+    out = np.empty((nq, d), np.float32)
+    if gname == "mixture":
+        centres = g.standard_normal((10, d)) * 2.0
+        for a in range(0, nq, CHUNK):
+            b = min(nq, a + CHUNK)
+            lab = qg.integers(0, 10, size=b - a)
+            out[a:b] = (centres[lab] + qg.standard_normal((b - a, d))).astype(np.float32)
+    elif gname == "sift_like":
+        W = g.standard_normal((16, d)) / np.sqrt(16)
+        for a in range(0, nq, CHUNK):
+            b = min(nq, a + CHUNK)
+            z = qg.standard_normal((b - a, 16))
+            eps = qg.standard_normal((b - a, d)) * 0.5
+            out[a:b] = np.rint(255.0 / (1.0 + np.exp(-(z @ W + eps)))).astype(np.float32)
+    else:
+        W = g.standard_normal((32, d)) / np.sqrt(32)
+        for a in range(0, nq, CHUNK):
+            b = min(nq, a + CHUNK)
+            z = qg.standard_normal((b - a, 32))
+            out[a:b] = (z @ W + qg.standard_normal((b - a, d)) * 0.1).astype(np.float32)
+    return out
