@@ -260,6 +260,55 @@ cng_status cng_nearest_centre_entry(const float *queries, int64_t nq, int32_t d,
                                     int32_t K, const uint32_t *entries, uint32_t *out_entry,
                                     void *workspace, size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------ serving */
+/* Continuous batching on the device (not in the paper).  cng_serve_start
+ * launches a persistent grid of `waves` wavefronts on a stream of its own;
+ * each wavefront repeatedly takes the next queued query (in submission
+ * order), runs the beam search of cng_search / cng_search_quantized with that
+ * query's k and L, and publishes the result.  Requests submitted while others
+ * run join the same grid as ring slots free up.  One ring slot holds one
+ * query (vector and results), so `capacity` slots bound the queries in flight
+ * and their memory: cng_serve_submit refuses (CNG_ECAPACITY) a request whose
+ * queries do not all fit in the next free slots; poll completed requests and
+ * retry.  Results of a query do not depend on what else is in flight.
+ * Rings and results live in coherent pinned host memory.  The grid ends on
+ * cng_serve_stop, or by itself after about ten seconds without work (a later
+ * poll then reports CNG_EDEVICE).  A server is used from one host thread. */
+typedef struct cng_server cng_server;
+
+typedef struct {
+    const float *points;    /* [n x d] float32 (re-rank / plain scoring) */
+    const void *vecs;       /* stored vectors scored by the search (== points for CNG_F32) */
+    int32_t dtype;          /* cng_dtype of vecs */
+    const float *scales;    /* fp8 scales or NULL */
+    int64_t n;
+    int32_t d;              /* 4..512, multiple of 4 */
+    const uint32_t *adj;    /* [n x W] */
+    int32_t W;
+    uint32_t entry;         /* default entry point */
+    int32_t waves;          /* persistent wavefronts (0: 4 per compute unit) */
+    int32_t capacity;       /* ring slots = most queries in flight (0: 4 x waves) */
+    int32_t max_k;          /* largest k of any request, <= 256 */
+    int32_t visited_log2;   /* 0 = 11 */
+} cng_serve_config;
+
+/* Device workspace (bytes) the server keeps for its lifetime. */
+size_t cng_serve_workspace_size(void);
+cng_status cng_serve_start(const cng_serve_config *cfg, void *workspace, size_t workspace_bytes,
+                           cng_server **server_host);
+/* Queue a request: queries_host [nq x d] float32, results k per query, beam L
+ * (max(L, k) <= 256); entries_host [nq] optional per-query entry points.
+ * Writes the request id.  CNG_ECAPACITY: not admitted now, nothing queued. */
+cng_status cng_serve_submit(cng_server *server, const float *queries_host, int32_t nq, int32_t k,
+                            int32_t L, const uint32_t *entries_host, uint64_t *req_host);
+/* done_host = 1 once every query of the request is complete; then ids_host /
+ * dists_host [nq x k] (may be NULL) receive the results and the request is
+ * retired.  done_host = 0 while pending. */
+cng_status cng_serve_poll(cng_server *server, uint64_t req, uint32_t *ids_host, float *dists_host,
+                          int32_t *done_host);
+/* End the grid and release the server. */
+cng_status cng_serve_stop(cng_server *server);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Message of the last non-OK status on the calling thread ("" if none). */

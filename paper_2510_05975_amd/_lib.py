@@ -88,6 +88,11 @@ _SIGS = {
                                     vp, sz, vp]),
     "cng_nearest_centre_workspace_size": (sz, [i64, i32, i32]),
     "cng_nearest_centre_entry": (C.c_int, [vp, i64, i32, vp, i32, vp, vp, vp, sz, vp]),
+    "cng_serve_workspace_size": (sz, []),
+    "cng_serve_start": (C.c_int, [C.c_void_p, vp, sz, C.POINTER(C.c_void_p)]),
+    "cng_serve_submit": (C.c_int, [vp, vp, i32, i32, i32, vp, C.POINTER(C.c_uint64)]),
+    "cng_serve_poll": (C.c_int, [vp, C.c_uint64, vp, vp, C.POINTER(i32)]),
+    "cng_serve_stop": (C.c_int, [vp]),
 }
 
 
@@ -392,6 +397,87 @@ def nearest_centre_entry(queries, centers, entries):
     _check("cng_nearest_centre_entry", lib().cng_nearest_centre_entry(
         _ptr(q), nq, d, _ptr(c), K, _ptr(_ids(entries)), _ptr(out), _ptr(ws), nb, _stream()))
     return out
+
+
+# ---------------------------------------------------------------- serving
+class ServeConfig(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("vecs", C.c_void_p), ("dtype", C.c_int32),
+                ("scales", C.c_void_p), ("n", C.c_int64), ("d", C.c_int32), ("adj", C.c_void_p),
+                ("W", C.c_int32), ("entry", C.c_uint32), ("waves", C.c_int32),
+                ("capacity", C.c_int32), ("max_k", C.c_int32), ("visited_log2", C.c_int32)]
+
+
+class Server:
+    """Continuous-batching search server (cng_serve_*): a persistent device
+    grid fed through pinned host rings.  Host arrays in, host arrays out."""
+
+    def __init__(self, points: torch.Tensor, adj: torch.Tensor, entry: int, store: "Store | None" = None,
+                 max_k: int = 100, waves: int = 0, capacity: int = 0, visited_log2: int = 0):
+        import numpy as np  # noqa: F401
+        x = _f32(points)
+        self._keep = [x, _ids(adj), store]
+        self.d = x.shape[1]
+        cfg = ServeConfig(x.data_ptr(), (store.vecs if store else x).data_ptr(),
+                          store.dtype if store else F32,
+                          store.scales.data_ptr() if (store and store.scales is not None) else None,
+                          x.shape[0], self.d, _ids(adj).data_ptr(), adj.shape[1], entry, waves,
+                          capacity, max_k, visited_log2)
+        self._ws = _ws(lib().cng_serve_workspace_size(), x.device)
+        torch.cuda.synchronize()
+        h = C.c_void_p(0)
+        _check("cng_serve_start", lib().cng_serve_start(C.byref(cfg), _ptr(self._ws),
+                                                        self._ws.numel(), C.byref(h)))
+        self._h = h
+        self.pending = {}
+
+    def submit(self, queries, k: int, L: int, entries=None):
+        """Returns a request id, or None when the request is not admitted now."""
+        import numpy as np
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        ent = None if entries is None else np.ascontiguousarray(entries, dtype=np.uint32)
+        rid = C.c_uint64(0)
+        st = lib().cng_serve_submit(self._h, q.ctypes.data, q.shape[0], k, L,
+                                    None if ent is None else ent.ctypes.data, C.byref(rid))
+        if st == -5:
+            return None
+        _check("cng_serve_submit", st)
+        self.pending[rid.value] = (q.shape[0], k)
+        return rid.value
+
+    def poll(self, req: int):
+        """(ids uint32 [nq, k], dists float32 [nq, k]) once complete, else None."""
+        import numpy as np
+        nq, k = self.pending[req]
+        ids = np.empty((nq, k), np.uint32)
+        dists = np.empty((nq, k), np.float32)
+        done = C.c_int32(0)
+        _check("cng_serve_poll", lib().cng_serve_poll(self._h, req, ids.ctypes.data,
+                                                      dists.ctypes.data, C.byref(done)))
+        if not done.value:
+            return None
+        del self.pending[req]
+        return ids, dists
+
+    def wait(self, req: int, timeout: float = 30.0):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.poll(req)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout:
+                raise TimeoutError(f"request {req} not complete after {timeout}s")
+
+    def stop(self):
+        if self._h:
+            _check("cng_serve_stop", lib().cng_serve_stop(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
 
 
 def u32(t: torch.Tensor):

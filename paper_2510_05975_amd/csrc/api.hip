@@ -30,6 +30,14 @@ cng_status fail(cng_status s, const char *fmt, ...)
     return s;
 }
 
+}  // namespace
+
+namespace cng {
+void set_error(const char *msg) { g_err = msg; }
+}  // namespace cng
+
+namespace {
+
 cng_status ok()
 {
     g_err.clear();

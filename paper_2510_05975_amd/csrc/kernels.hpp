@@ -29,6 +29,33 @@ struct SearchArgs {
 };
 
 hipError_t launch_search(const SearchArgs &a, hipStream_t stream);
+
+// serving loop (persistent kernel; ring and results in coherent pinned host memory)
+struct ServeRing {
+    uint64_t tail;  // items published by the host
+    uint64_t stop;  // non-zero: leave the loop
+    uint64_t pad[6];
+};
+struct ServeItem {   // read by the device as four uint32 words
+    uint32_t req;    // request id (host bookkeeping)
+    uint32_t k, L;   // results wanted and beam width
+    uint32_t entry;  // entry point of the search
+};
+struct ServeArgs {
+    SearchArgs base;            // graph, vectors, storage, visited table size
+    ServeRing *ring;
+    const ServeItem *items;     // [cap]
+    uint64_t cap;
+    const float *payload;       // [cap x d] query vectors
+    uint32_t *out_ids;          // [cap x max_k]
+    float *out_dists;           // [cap x max_k]
+    uint64_t *done;             // [cap]: t + 1 once item t is complete
+    unsigned long long *head;   // device memory: next item to claim
+    uint32_t max_k;
+    uint32_t idle_limit;
+};
+hipError_t launch_serve(const ServeArgs &a, int waves, hipStream_t stream);
+size_t serve_lds_per_wave(int d, int vlog2);
 int search_default_vlog2(int Leff);
 size_t search_lds_per_wave(int Leff, int vlog2);
 

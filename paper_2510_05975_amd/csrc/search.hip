@@ -334,6 +334,112 @@ KernelFn pick_store(int d, int qs, int st)
                                                            : pick_kernel<VEC, 0>(d, qs);
 }
 
+
+// ---------------------------------------------------------------- serving loop
+// A persistent grid: every wavefront claims work items in order from a ring
+// that the host fills (coherent pinned host memory), runs the beam search of
+// one query with that item's k and L, writes the results to pinned host
+// memory and marks the item done with a system-scope release store.  The host
+// publishes items by advancing `tail` (release); a wave whose claimed item is
+// not yet published sleeps and re-checks `tail` and `stop`, and leaves after
+// `idle_limit` empty checks, so every wave ends even if the host goes away.
+__device__ __forceinline__ uint64_t sys_load_u64(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t sys_load_u32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <int G, int RND, bool VEC, int QS, int UB, int ST>
+__global__ __launch_bounds__(256) void serve_kernel(ServeArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int qcap = 64 * QS;
+    const size_t per_wave = wave_lds_bytes(qcap, a.base.vlog2) + (size_t)a.base.d * 4 + 16;
+    unsigned char *base = smem + (size_t)wave * per_wave;
+    WaveLds s;
+    s.qa = reinterpret_cast<uint64_t *>(base);
+    s.tmp = s.qa + qcap;
+    s.dsc = reinterpret_cast<float *>(s.tmp + 64);
+    s.cid = reinterpret_cast<uint32_t *>(s.dsc + 64);
+    s.vis = s.cid + 64;
+    float *qbuf = reinterpret_cast<float *>(s.vis + ((size_t)1 << a.base.vlog2));
+    uint32_t *ebuf = reinterpret_cast<uint32_t *>(qbuf + a.base.d);
+    (void)wpb;
+
+    uint32_t idle = 0;
+    for (;;) {
+        uint64_t t = 0;
+        if (lane == 0) t = atomicAdd(a.head, 1ull);
+        t = ((uint64_t)__shfl((uint32_t)(t >> 32), 0, 64) << 32) | __shfl((uint32_t)t, 0, 64);
+        for (;;) {  // wait until item t is published
+            int state = 0;  // 1: ready, 2: leave
+            if (lane == 0) {
+                if (sys_load_u64(&a.ring->tail) > t) state = 1;
+                else if (sys_load_u64(&a.ring->stop) != 0 || ++idle > a.idle_limit) state = 2;
+            }
+            state = __shfl(state, 0, 64);
+            if (state == 1) break;
+            if (state == 2) return;
+            __builtin_amdgcn_s_sleep(64);
+        }
+        idle = 0;
+        const uint64_t slot = t % a.cap;
+        const ServeItem *item = a.items + slot;
+        // item fields and the query vector, read through to host memory
+        uint32_t f[1] = {0};
+        if (lane < 4) f[0] = sys_load_u32(reinterpret_cast<const uint32_t *>(item) + lane);
+        const uint32_t k = (uint32_t)__shfl((int)f[0], 1, 64);
+        const uint32_t L = (uint32_t)__shfl((int)f[0], 2, 64);
+        const uint32_t entry = (uint32_t)__shfl((int)f[0], 3, 64);
+        const float *qsrc = a.payload + slot * (uint64_t)a.base.d;
+        for (int i = lane; i < a.base.d; i += 64)
+            qbuf[i] = __uint_as_float(sys_load_u32(reinterpret_cast<const uint32_t *>(qsrc) + i));
+        if (lane == 0) ebuf[0] = entry;
+        wave_sync();
+        SearchArgs q = a.base;
+        q.queries = qbuf;
+        q.query_ids = nullptr;
+        q.nq = 1;
+        q.k = (int)k;
+        q.Leff = (int)(L > k ? L : k);
+        q.entries = ebuf;
+        q.per_query_entry = 0;
+        q.ids = a.out_ids + slot * (uint64_t)a.max_k;
+        q.dists = a.out_dists + slot * (uint64_t)a.max_k;
+        q.hops = nullptr;
+        q.ndc = nullptr;
+        if (q.k >= 1 && q.k <= a.max_k && q.Leff <= qcap) beam_query<G, RND, VEC, QS, UB, ST>(q, 0, s);
+        wave_sync();
+        __threadfence_system();
+        if (lane == 0) __hip_atomic_store(&a.done[slot], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+using ServeFn = void (*)(ServeArgs);
+
+template <int G, int RND, int ST>
+ServeFn serve_fn()
+{
+    constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : 8;
+    return serve_kernel<G, RND, true, 4, UB, ST>;
+}
+
+template <int ST>
+ServeFn pick_serve(int d)
+{
+    if (d <= 32) return serve_fn<8, 1, ST>();
+    if (d <= 64) return serve_fn<16, 1, ST>();
+    int rnd = (d + 127) / 128;
+    if (rnd <= 1) return serve_fn<32, 1, ST>();
+    if (rnd <= 2) return serve_fn<32, 2, ST>();
+    return serve_fn<32, 4, ST>();
+}
 }  // namespace
 
 // Measured on 1M x 128 (beam 48..128): a 1024-slot table beats larger ones,
@@ -368,6 +474,24 @@ hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
     const int64_t blocks = (a.nq + wpb - 1) / wpb;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), (unsigned)(wpb * per_wave),
                        stream, b);
+    return hipGetLastError();
+}
+
+size_t serve_lds_per_wave(int d, int vlog2)
+{
+    return wave_lds_bytes(256, vlog2) + (size_t)d * 4 + 16;
+}
+
+// The persistent serving grid: `waves` wavefronts, 4 per workgroup.  Needs
+// d % 4 == 0, d <= 512, beams up to 256 entries (one template per storage).
+hipError_t launch_serve(const ServeArgs &a, int waves, hipStream_t stream)
+{
+    ServeFn fn = a.base.store == 1 ? pick_serve<1>(a.base.d)
+               : a.base.store == 2 ? pick_serve<2>(a.base.d) : pick_serve<0>(a.base.d);
+    const size_t per_wave = serve_lds_per_wave(a.base.d, a.base.vlog2);
+    const int wpb = 4;
+    const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * wpb), (unsigned)(wpb * per_wave), stream, a);
     return hipGetLastError();
 }
 
