@@ -49,6 +49,11 @@ def parse():
                     help="time only the search leg (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (scale for HBM byte counters)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the bf16/fp8, learned-entry and serving legs")
+    ap.add_argument("--learn-n", type=int, default=1_000_000, help="base size of the learned-entry leg")
+    ap.add_argument("--learn-train", type=int, default=200_000, help="training queries of the learned-entry leg")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-qps", type=str, default="50000,200000")
     return ap.parse_args()
 
 
@@ -215,7 +220,233 @@ def main():
                                  "traffic": None}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, cng.u32(g.adj), g.entry, k, L, a.cpu_seconds)
+    if not a.no_forms and not a.search_only:
+        fp32_by_L = {r["L"]: r for r in sweep}
+        forms = {}
+        for name, dt in (("bf16", cng.BF16), ("fp8", cng.FP8)):
+            forms[name] = quant_form(cng, torch, x, q, xd, qd, g, dt, gt_ids, gt_dk, k, cfg["L"],
+                                     fp32_by_L, a.search_reps)
+            print(f"# form {name} {forms[name]}", file=sys.stderr, flush=True)
+        forms["serving"] = serving_form(cng, torch, x, q, xd, g, gt_ids, a)
+        print(f"# serving {forms['serving']}", file=sys.stderr, flush=True)
+        forms["learned_entry"] = learned_form(cng, torch, a)
+        out["forms"] = forms
     print(json.dumps(out))
+
+
+def timed(torch, fn, reps):
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record(st)
+        fn()
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def quant_form(cng, torch, x, q, xd, qd, g, dtype, gt_ids, gt_dk, k, Ls, fp32_by_L, reps):
+    """bf16 / fp8 storage, reduced-precision beam, float32 re-rank of the beam."""
+    t0 = time.perf_counter()
+    st = cng.quantize(xd, dtype)
+    torch.cuda.synchronize()
+    qsec = time.perf_counter() - t0
+    n, d = x.shape
+    nq = q.shape[0]
+    W = g.adj.shape[1]
+    sweep, chosen = [], None
+    for L in Ls:
+        ids, dists, hops, ndc = cng.search_quantized(xd, st, g.adj, qd, k, L, g.entry, visited_log2=14,
+                                                     stats=True)
+        torch.cuda.synchronize()
+        s_, tw = recall(cng.u32(ids), gt_ids, gt_dk, dists.cpu().numpy())
+        row = dict(L=L, recall_tie=round(tw, 4), recall_strict=round(s_, 4),
+                   hops=float(hops.float().mean()), ndc=float(ndc.float().mean()))
+        sweep.append(row)
+        if tw >= 0.95:
+            chosen = (row, cng.u32(ids), dists.cpu().numpy())
+            break
+    if chosen is None:
+        return {"sweep": sweep, "note": "recall 0.95 not reached"}
+    row, ids, dists = chosen
+    L = row["L"]
+    ms = timed(torch, lambda: cng.search_quantized(xd, st, g.adj, qd, k, L, g.entry), reps)
+    b = 2 if dtype == cng.BF16 else 1
+    bytes_q = row["ndc"] * (d * b + (4 if dtype == cng.FP8 else 0)) + row["hops"] * W * 4 + \
+        max(L, k) * d * 4 + d * 4 + k * 8
+    achieved = bytes_q * nq / (ms / 1e3) / 1e9
+    # distance error of the returned (float32 re-ranked) distances against float64
+    m = min(nq, 2000)
+    X64 = x.astype(np.float64)
+    ref = np.sqrt(((X64[ids[:m]] - q[:m, None, :].astype(np.float64)) ** 2).sum(-1))
+    ok = ref > 0
+    rel = np.abs(dists[:m].astype(np.float64) - ref)[ok] / ref[ok]
+    base = fp32_by_L.get(L)
+    return {"L": L, "qps": round(nq / (ms / 1e3), 1), "search_ms": round(ms, 4),
+            "recall@10": row["recall_tie"], "recall@10_strict": row["recall_strict"],
+            "recall_loss_vs_fp32_same_L": None if base is None else
+            round(base["recall_tie"] - row["recall_tie"], 4),
+            "dist_rel_err_vs_fp64": {"max": float(rel.max()), "mean": float(rel.mean())},
+            "hops_mean": row["hops"], "ndc_mean": row["ndc"], "quantize_s": round(qsec, 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+            "sweep": sweep}
+
+
+def serving_form(cng, torch, x, q, xd, g, gt_ids, a):
+    """Poisson request stream into the device serving loop (fp8 storage, float32
+    re-rank): 1-64 queries per request, k in {1, 10, 100}, L in {32, 64, 128, 256}."""
+    st = cng.quantize(xd, cng.FP8)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(123))
+    res = {"index": "same graph, fp8-E4M3 storage + float32 re-rank", "runs": []}
+    for target in [float(v) for v in a.serve_qps.split(",")]:
+        with cng.Server(xd, g.adj, g.entry, store=st, max_k=100) as srv:
+            mean_q = 32.5
+            rate = target / mean_q               # requests per second
+            t_end = a.serve_seconds
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * t_end * 1.2) + 10))
+            arrivals = arrivals[arrivals < t_end]
+            specs = [(int(rng.integers(1, 65)), int(rng.choice([1, 10, 100])),
+                      int(rng.choice([32, 64, 128, 256]))) for _ in arrivals]
+            qsel = [rng.integers(0, len(q), nq_) for nq_, _, _ in specs]
+            lat, done_q, hits, tot10 = [], 0, 0, 0
+            backlog, outstanding = [], []   # (arrival, idx)
+            i = 0
+            t0 = time.perf_counter()
+            while i < len(arrivals) or backlog or outstanding:
+                now = time.perf_counter() - t0
+                while i < len(arrivals) and arrivals[i] <= now:
+                    backlog.append(i)
+                    i += 1
+                while backlog:
+                    j = backlog[0]
+                    nq_, k_, L_ = specs[j]
+                    r = srv.submit(q[qsel[j]], k_, L_)
+                    if r is None:
+                        break
+                    outstanding.append((j, r))
+                    backlog.pop(0)
+                keep = []
+                for j, r in outstanding:
+                    out = srv.poll(r)
+                    if out is None:
+                        keep.append((j, r))
+                        continue
+                    t = time.perf_counter() - t0
+                    lat.append(t - arrivals[j])
+                    done_q += specs[j][0]
+                    if specs[j][1] == 10:
+                        for row, qi in zip(out[0], qsel[j]):
+                            hits += len(set(row.tolist()) & set(gt_ids[qi].tolist()))
+                            tot10 += 10
+                outstanding = keep
+                if now > t_end + 30:
+                    break
+            wall = time.perf_counter() - t0
+        lat_ms = np.array(lat) * 1e3
+        res["runs"].append({"offered_qps": target, "requests": len(lat), "queries": done_q,
+                            "achieved_qps": round(done_q / wall, 1),
+                            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                            "recall@10_k10_requests": round(hits / max(tot10, 1), 4)})
+    return res
+
+
+def learned_form(cng, torch, a):
+    """vMF workload (unit vectors, 100 centres, kappa 50): k-means entry nodes,
+    labels from the plain search, MLP 96-256-256-1024 trained on the GPU;
+    QPS at recall@10 >= 0.95 for medoid / nearest-centre / MLP entries, float32
+    and bf16 scoring.  Entry inference time is inside the timed region."""
+    import workloads
+    from paper_2510_05975_amd import _lib as Lb, learned
+    cfg = workloads.CONFIGS[4]
+    n, d, k, nq = a.learn_n, cfg["d"], cfg["k"], cfg["nq"]
+    x, q = workloads.generate(4, n=n, nq=nq)
+    tr = workloads.fresh_queries(4, a.learn_train, stream=1)
+    va = workloads.fresh_queries(4, 5000, stream=2)
+    xd, qd, trd, vad = (torch.from_numpy(v).to("cuda:0") for v in (x, q, tr, va))
+    t0 = time.perf_counter()
+    g = cng.build(xd, cfg["R"], cfg["C"], cfg["alpha"], cfg["tau"])
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    gt_t, gD, _ = cng.knn(qd, xd, k)
+    gt = cng.u32(gt_t)
+    gdk = np.sqrt(gD.cpu().numpy()[:, k - 1]).astype(np.float32)
+    K, H = 1024, 256
+    t0 = time.perf_counter()
+    cent, ents = learned.kmeans_entries(xd, K, iters=20, seed=1)
+    labels = Lb.entry_labels(xd, g.adj, g.entry, trd, 64, ents)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    model = learned.EntryModel(d, H, K, torch.from_numpy(learned.init_params(d, H, K, 7)).to("cuda:0"),
+                               ents, cent, g.entry, theta=0.0, precision=1)
+    t0 = time.perf_counter()
+    learned.train(model, trd, labels, epochs=3, batch=1024, lr=1e-3, seed=3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    # held-out accuracy of the label and the gate threshold on validation queries
+    vlab = Lb.entry_labels(xd, g.adj, g.entry, vad, 64, ents)
+    Z = Lb.mlp_logits(model.params, d, H, K, vad, 1)
+    acc = float((Z.argmax(1).int() == vlab).float().mean())
+    st16 = cng.quantize(xd, cng.BF16)
+    torch.cuda.synchronize()
+
+    def run(entry_fn, store, L):
+        def go():
+            e = entry_fn()
+            if store is None:
+                return cng.search(xd, g.adj, qd, k, L, e)
+            return cng.search_quantized(xd, store, g.adj, qd, k, L, e)
+        ids, dd, _, _ = go()
+        torch.cuda.synchronize()
+        _, tw = recall(cng.u32(ids), gt, gdk, dd.cpu().numpy())
+        return tw, go
+
+    def best_theta():
+        best = (-1.0, 0.0)
+        vgt_t, vD, _ = cng.knn(vad, xd, k)
+        vgt = cng.u32(vgt_t)
+        vdk = np.sqrt(vD.cpu().numpy()[:, k - 1]).astype(np.float32)
+        for th in (0.0, 0.05, 0.1, 0.2, 0.3):
+            e, _ = model.predict(vad, th)
+            ids, dd, _, _ = cng.search(xd, g.adj, vad, k, 32, e)
+            torch.cuda.synchronize()
+            _, tw = recall(cng.u32(ids), vgt, vdk, dd.cpu().numpy())
+            if tw > best[0] + 1e-4:
+                best = (tw, th)
+        return best[1]
+
+    model.theta = best_theta()
+    variants = {
+        "fp32_medoid": (lambda: g.entry, None),
+        "fp32_nearest_centre": (lambda: Lb.nearest_centre_entry(qd, cent, ents), None),
+        "fp32_mlp": (lambda: model.predict(qd)[0], None),
+        "bf16_medoid": (lambda: g.entry, st16),
+        "bf16_mlp": (lambda: model.predict(qd)[0], st16),
+    }
+    out = {"workload": cfg["name"].replace("10m", f"{n // 1000}k"), "n": n, "d": d, "nq": nq,
+           "entries_K": K, "mlp": f"{d}-{H}-{H}-{K}", "params": Lb.mlp_param_count(d, H, K),
+           "train_pairs": a.learn_train, "epochs": 3, "train_s": round(train_s, 2),
+           "kmeans_and_labels_s": round(prep_s, 2), "build_s": round(build_s, 2),
+           "final_loss": model.history[-1][1], "val_label_accuracy": round(acc, 4),
+           "theta": model.theta, "variants": {}}
+    for name, (efn, store) in variants.items():
+        got = None
+        curve = []
+        for L in cfg["L"]:
+            tw, go = run(efn, store, L)
+            curve.append((L, round(tw, 4)))
+            if tw >= 0.95:
+                ms = timed(torch, go, a.search_reps)
+                got = {"L": L, "recall@10": round(tw, 4), "qps": round(nq / (ms / 1e3), 1),
+                       "ms": round(ms, 4)}
+                break
+        out["variants"][name] = dict(got or {"note": "recall 0.95 not reached"}, curve=curve)
+        print(f"# learned {name} {out['variants'][name]}", file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(x, q, adj, entry, k, L, budget_s):

@@ -59,6 +59,54 @@ __device__ __forceinline__ double group_sum_f64(double v)
     return v;
 }
 
+// Lane exchange v[lane ^ OFF] within aligned groups of 32 lanes: DPP quad
+// permutations for offsets 1 and 2, ds_swizzle (xor mode) above.
+template <int OFF>
+__device__ __forceinline__ float xor_lane(float v)
+{
+    const int x = __float_as_int(v);
+    int r;
+    if (OFF == 1) r = __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);       // quad_perm [1,0,3,2]
+    else if (OFF == 2) r = __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    else r = __builtin_amdgcn_ds_swizzle(x, 0x1F | (OFF << 10));                      // and 0x1F, xor OFF
+    return __int_as_float(r);
+}
+
+// Fixed-order sums of UB vectors at once.  v[t] holds this lane's partial sum
+// of vector t (lanes of a group of G, G <= 32, UB <= G).  Each step pairs lane
+// l with lane l ^ off, the pairing of the butterfly, so every sum is the
+// butterfly of one vector, bit for bit; but a step that still holds several
+// vectors per lane sends half of them to the partner and keeps the other
+// half (recursive halving), so the UB butterflies cost about UB exchanges in
+// total instead of UB * log2(G).  On return, lanes
+// [t * (G / UB), (t + 1) * (G / UB)) of the group hold the sum of vector t.
+template <int G, int UB, int OFF, int N>
+__device__ __forceinline__ void halve_step(float (&v)[UB], int gl)
+{
+    if constexpr (OFF >= 1) {
+        if constexpr (N > 1) {
+            const bool hi = (gl & OFF) != 0;
+#pragma unroll
+            for (int j = 0; j < N / 2; ++j) {
+                const float keep = hi ? v[j + N / 2] : v[j];
+                const float send = hi ? v[j] : v[j + N / 2];
+                v[j] = keep + xor_lane<OFF>(send);
+            }
+            halve_step<G, UB, OFF / 2, N / 2>(v, gl);
+        } else {
+            v[0] = v[0] + xor_lane<OFF>(v[0]);
+            halve_step<G, UB, OFF / 2, 1>(v, gl);
+        }
+    }
+}
+
+template <int G, int UB>
+__device__ __forceinline__ void group_sums(float (&v)[UB], int gl)
+{
+    static_assert(UB <= G && G <= 32, "group_sums: UB <= G <= 32");
+    halve_step<G, UB, G / 2, UB>(v, gl);
+}
+
 // Partial sum of one lane for the fixed-order distance of two float4-chunked
 // vectors: chunk r of lane gl covers elements (r*32 + gl)*4 .. +3.
 __device__ __forceinline__ float chunk_fma(float4 a, float4 b, float acc)
@@ -184,6 +232,38 @@ __device__ __forceinline__ float4 load_stored(const void *__restrict__ base, siz
         }
         return v;
     }
+}
+
+// Raw words of chunk r of lane gl of a stored row (no use of the loaded value,
+// so a batch of these loads stays in flight together); decode_chunk turns them
+// into the float32 values.  VEC layout only (d % 4 == 0, aligned rows).
+template <int ST> struct RawChunk;
+template <> struct RawChunk<0> { typedef float4 type; };
+template <> struct RawChunk<1> { typedef uint2 type; };
+template <> struct RawChunk<2> { typedef uint32_t type; };
+
+template <int ST>
+__device__ __forceinline__ typename RawChunk<ST>::type load_raw(const void *__restrict__ base, size_t row,
+                                                                int d, int r, int gl)
+{
+    typedef typename RawChunk<ST>::type T;
+    const int i = (r * 32 + gl) * 4;
+    if (i >= d) return T{};
+    if (ST == 0) return *reinterpret_cast<const T *>(reinterpret_cast<const float *>(base) + row * d + i);
+    if (ST == 1) return *reinterpret_cast<const T *>(reinterpret_cast<const uint16_t *>(base) + row * d + i);
+    return *reinterpret_cast<const T *>(reinterpret_cast<const uint8_t *>(base) + row * d + i);
+}
+
+__device__ __forceinline__ float4 decode_chunk(float4 w, float) { return w; }
+__device__ __forceinline__ float4 decode_chunk(uint2 w, float)
+{
+    return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+}
+__device__ __forceinline__ float4 decode_chunk(uint32_t w, float scale)
+{
+    return make_float4(e4m3_value(w & 0xFFu) * scale, e4m3_value((w >> 8) & 0xFFu) * scale,
+                       e4m3_value((w >> 16) & 0xFFu) * scale, e4m3_value(w >> 24) * scale);
 }
 
 // Bitonic sort of n (power of two) 64-bit keys in LDS by one wavefront.

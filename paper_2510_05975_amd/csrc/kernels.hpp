@@ -51,6 +51,7 @@ struct ServeArgs {
     float *out_dists;           // [cap x max_k]
     uint64_t *done;             // [cap]: t + 1 once item t is complete
     unsigned long long *head;   // device memory: next item to claim
+    uint64_t *mirror;           // device memory: [0] last tail seen, [1] stop seen
     uint32_t max_k;
     uint32_t idle_limit;
 };

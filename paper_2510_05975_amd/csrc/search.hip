@@ -79,6 +79,69 @@ __device__ __forceinline__ int lower_bound_keys(const uint64_t *arr, int cnt, ui
     return lo;
 }
 
+// Fixed-order squared distances of the stored vectors cid[0..m) to the
+// query (chunks qr, this lane's share) into dsc[0..m).  Group grp of G lanes
+// takes vectors b + t * NG + grp for t < UB; all loads of a batch are issued
+// before any sum (a batch's trip count is uniform across the wavefront), then
+// the UB sums are formed together by group_sums.
+template <int G, int RND, bool VEC, int UB, int ST>
+__device__ __forceinline__ void gather_dists(const void *__restrict__ vecs, const float *__restrict__ scales,
+                                             int d, const uint32_t *cid, int m, const float4 (&qr)[RND],
+                                             float *dsc)
+{
+    constexpr int NG = 64 / G;
+    const int lane = lane_id();
+    const int grp = lane / G, gl = lane % G;
+    for (int b = 0; b < m; b += NG * UB) {
+        // Loads only: nothing in a guarded block uses a loaded value, so no
+        // wait separates the loads of a batch.  A group past the end of the
+        // list re-reads vector b and its sum is never written.
+        float acc[UB];
+        if (VEC) {
+            typename RawChunk<ST>::type raw[UB][RND];
+            float sc[UB];
+#pragma unroll
+            for (int t = 0; t < UB; ++t) {
+                if (b + t * NG < m) {  // uniform: some group still has a vector
+                    const int c = b + t * NG + grp;
+                    const uint32_t id = cid[c < m ? c : b];
+                    sc[t] = ST == 2 ? scales[id] : 1.f;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) raw[t][r] = load_raw<ST>(vecs, id, d, r, gl);
+                } else {
+                    sc[t] = 0.f;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) raw[t][r] = typename RawChunk<ST>::type{};
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < UB; ++t) {
+                acc[t] = 0.f;
+#pragma unroll
+                for (int r = 0; r < RND; ++r) acc[t] = chunk_fma(decode_chunk(raw[t][r], sc[t]), qr[r], acc[t]);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < UB; ++t) {
+                acc[t] = 0.f;
+                if (b + t * NG < m) {
+                    const int c = b + t * NG + grp;
+                    const uint32_t id = cid[c < m ? c : b];
+                    const float sc = ST == 2 ? scales[id] : 1.f;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r)
+                        acc[t] = chunk_fma(load_stored<ST, VEC>(vecs, id, d, r, gl, sc), qr[r], acc[t]);
+                }
+            }
+        }
+        group_sums<G, UB>(acc, gl);
+        constexpr int SPAN = G / UB;  // lanes holding one vector's sum
+        const int t = gl / SPAN;
+        const int c = b + t * NG + grp;
+        if (gl % SPAN == 0 && c < m) dsc[c] = acc[0];
+    }
+}
+
 struct WaveLds {
     uint64_t *qa, *tmp;
     float *dsc;
@@ -162,31 +225,7 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
             }
             wave_sync();
             // ---- distances: G lanes per vector, NG vectors per instruction
-            for (int b = 0; b < m; b += NG * UB) {
-                float4 xv[UB][RND];
-#pragma unroll
-                for (int t = 0; t < UB; ++t) {
-                    int c = b + t * NG + grp;
-                    if (c < m) {
-                        const uint32_t id = s.cid[c];
-                        const float sc = ST == 2 ? a.scales[id] : 1.f;
-#pragma unroll
-                        for (int r = 0; r < RND; ++r) xv[t][r] = load_stored<ST, VEC>(a.vecs, id, d, r, gl, sc);
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < RND; ++r) xv[t][r] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < UB; ++t) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int r = 0; r < RND; ++r) acc = chunk_fma(xv[t][r], qr[r], acc);
-                    acc = group_sum<G>(acc);
-                    int c = b + t * NG + grp;
-                    if (gl == 0 && c < m) s.dsc[c] = acc;
-                }
-            }
+            gather_dists<G, RND, VEC, UB, ST>(a.vecs, a.scales, d, s.cid, m, qr, s.dsc);
             wave_sync();
             ndc += (uint32_t)m;
             // ---- merge the m new keys into the beam (Algorithm 1: union, keep the L closest)
@@ -241,17 +280,9 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
         // ---- re-rank the converged beam with the float32 vectors
         for (int b0 = 0; b0 < qn; b0 += 64) {
             const int cnt = qn - b0 < 64 ? qn - b0 : 64;
-            for (int b = 0; b < cnt; b += NG) {
-                const int c = b + grp;
-                float acc = 0.f;
-                if (c < cnt) {
-                    const float *xr = a.points + (size_t)key_id(qa[b0 + c]) * d;
-#pragma unroll
-                    for (int r = 0; r < RND; ++r) acc = chunk_fma(load_chunk<VEC>(xr, d, r, gl), qr[r], acc);
-                }
-                acc = group_sum<G>(acc);
-                if (gl == 0 && c < cnt) s.dsc[c] = acc;
-            }
+            if (lane < cnt) s.cid[lane] = key_id(qa[b0 + lane]);
+            wave_sync();
+            gather_dists<G, RND, VEC, UB, 0>(a.points, nullptr, d, s.cid, cnt, qr, s.dsc);
             wave_sync();
             if (lane < cnt) qa[b0 + lane] = make_key(s.dsc[lane], key_id(qa[b0 + lane]));
             wave_sync();
@@ -304,7 +335,7 @@ using KernelFn = void (*)(SearchArgs);
 template <int G, int RND, bool VEC, int ST>
 KernelFn pick_qs(int qs)
 {
-    constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : 8;
+    constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : G / 2;
     switch (qs) {
     case 1: return search_kernel<G, RND, VEC, 1, UB, ST>;
     case 2: return search_kernel<G, RND, VEC, 2, UB, ST>;
@@ -378,15 +409,35 @@ __global__ __launch_bounds__(256) void serve_kernel(ServeArgs a)
         if (lane == 0) t = atomicAdd(a.head, 1ull);
         t = ((uint64_t)__shfl((uint32_t)(t >> 32), 0, 64) << 32) | __shfl((uint32_t)t, 0, 64);
         for (;;) {  // wait until item t is published
+            // Only the wave holding the oldest unpublished item reads host
+            // memory; it copies tail / stop into device memory (mirror[0] /
+            // mirror[1]) where the other waves wait without crossing the bus.
             int state = 0;  // 1: ready, 2: leave
             if (lane == 0) {
-                if (sys_load_u64(&a.ring->tail) > t) state = 1;
-                else if (sys_load_u64(&a.ring->stop) != 0 || ++idle > a.idle_limit) state = 2;
+                uint64_t seen = __hip_atomic_load(&a.mirror[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (seen > t) {
+                    state = 1;
+                } else if (__hip_atomic_load(&a.mirror[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+                    state = 2;
+                } else {
+                    if (seen == t) {  // this wave is next in line: poll the host
+                        const uint64_t tail = sys_load_u64(&a.ring->tail);
+                        if (tail > seen) {
+                            atomicMax(reinterpret_cast<unsigned long long *>(&a.mirror[0]),
+                                      (unsigned long long)tail);
+                            state = 1;
+                        } else if (sys_load_u64(&a.ring->stop) != 0) {
+                            __hip_atomic_store(&a.mirror[1], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            state = 2;
+                        }
+                    }
+                    if (state == 0 && ++idle > a.idle_limit) state = 2;
+                }
             }
             state = __shfl(state, 0, 64);
             if (state == 1) break;
             if (state == 2) return;
-            __builtin_amdgcn_s_sleep(64);
+            __builtin_amdgcn_s_sleep(16);
         }
         idle = 0;
         const uint64_t slot = t % a.cap;
@@ -426,7 +477,7 @@ using ServeFn = void (*)(ServeArgs);
 template <int G, int RND, int ST>
 ServeFn serve_fn()
 {
-    constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : 8;
+    constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : G / 2;
     return serve_kernel<G, RND, true, 4, UB, ST>;
 }
 

@@ -131,7 +131,7 @@ cng_status cng_serve_start(const cng_serve_config *c, void *workspace, size_t ws
     if (e == hipSuccess) e = pinned(&s->out_dists, &ddist, (size_t)cap * c->max_k);
     if (e == hipSuccess) e = pinned(&s->done, &ddone, (size_t)cap);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMemsetAsync(workspace, 0, 8, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(workspace, 0, 64, s->stream);
     if (e != hipSuccess) {
         release_all(s);
         delete s;
@@ -154,8 +154,9 @@ cng_status cng_serve_start(const cng_serve_config *c, void *workspace, size_t ws
     a.out_dists = ddist;
     a.done = ddone;
     a.head = (unsigned long long *)workspace;
+    a.mirror = (uint64_t *)workspace + 2;
     a.max_k = (uint32_t)c->max_k;
-    a.idle_limit = 1u << 22;  // about ten seconds without work ends the grid
+    a.idle_limit = 1u << 23;  // about ten seconds without work ends the grid
     e = cng::launch_serve(a, waves, s->stream);
     if (e != hipSuccess) {
         release_all(s);
