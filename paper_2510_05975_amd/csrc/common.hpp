@@ -260,10 +260,14 @@ __device__ __forceinline__ float4 decode_chunk(uint2 w, float)
     return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
                        __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
 }
+// fp8: the gfx950 conversion instruction widens two E4M3 codes per call
+// (exact); the product with the scale is one float32 rounding, as in the
+// element-wise definition above.
 __device__ __forceinline__ float4 decode_chunk(uint32_t w, float scale)
 {
-    return make_float4(e4m3_value(w & 0xFFu) * scale, e4m3_value((w >> 8) & 0xFFu) * scale,
-                       e4m3_value((w >> 16) & 0xFFu) * scale, e4m3_value(w >> 24) * scale);
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+    return make_float4(lo[0] * scale, lo[1] * scale, hi[0] * scale, hi[1] * scale);
 }
 
 // Bitonic sort of n (power of two) 64-bit keys in LDS by one wavefront.
