@@ -65,6 +65,24 @@ def test_prune_hand_worked_cases():
             assert got == case["expect"], (mode, case)
 
 
+def test_prune_near_tie_keeps_tau():
+    """Float32 near-ties of Eq. (1) are re-decided in float64 with the same tau.
+    p = 0, u = 3, v = 1 on a line: d(p,u) = 3, d(u,v) = 2, alpha = 1, so the
+    right side is 2 + 2 tau.  tau = 0.5 is an exact tie (u kept); tau just below
+    0.5 rounds to 0.5 in float32, so only the float64 re-check with the given tau
+    prunes u."""
+    pts = np.array([[0.0], [1.0], [3.0]], np.float32)
+    C = np.full((3, 2), NONE, np.uint32)
+    CD = np.full((3, 2), np.inf)
+    C[0] = [1, 2]
+    CD[0] = [1.0, 9.0]
+    for mode in (oracle.FP32, oracle.FP64):
+        for tau, expect in ((0.5, [1, 2]), (0.499999999, [1]), (0.500000001, [1, 2]),
+                            (0.0, [1])):
+            adj = oracle.prune(pts, C, CD, R=2, alpha=1.0, tau=tau, mode=mode)
+            assert [int(v) for v in adj[0] if v != NONE] == expect, (mode, tau)
+
+
 def _prune_setup(n=400, d=8, C=40, seed=4):
     x, _ = workloads.uniform_cube(n, 1, d, seed=seed)
     cand, D = oracle.knn(x, x, C, exclude_self=True, mode=oracle.FP64)
@@ -167,6 +185,14 @@ def test_medoid_is_point_nearest_centroid():
         order = np.argsort(dd)
         assert dd[order[1]] - dd[order[0]] > 1e-9 * dd[order[0]]
         assert oracle.medoid(x) == order[0]
+
+
+def test_medoid_tiny_hand_worked():
+    """Points 1, 3, 8: centroid 4, nearest point 3 (id 1); a centroid of the sum
+    (12) or of sum / (n - 1) (6) would pick 8 (id 2)."""
+    assert oracle.medoid(np.array([[1.0], [3.0], [8.0]], np.float32)) == 1
+    x = np.array([[1.0, 0.0], [3.0, 1.0], [8.0, -1.0]], np.float32)   # centroid (4, 0)
+    assert oracle.medoid(x) == 1
 
 
 def test_medoid_tie_goes_to_smaller_id():
