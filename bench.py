@@ -31,6 +31,27 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_TFLOPS = 157.3
 BF16_MFMA_TFLOPS = 2500.0
 
+# Memory traffic of the timed float32 search launch from two rocprofv3 --pmc runs
+# (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain
+# elementwise kernel of known size gives), in bytes per launch, keyed by workload
+# and beam width.  Valid only while the search kernel's sources hash to `src`.
+SEARCH_TRAFFIC = {("sift_like_1m", 96): dict(bytes=12.988e9, src="c5fee48999dae67c")}
+KERNEL_SOURCES = ("paper_2510_05975_amd/csrc/search.hip", "paper_2510_05975_amd/csrc/common.hpp")
+
+
+def search_traffic(workload, L):
+    """Counter-measured bytes per launch, or None if not measured for this
+    workload or if the kernel has changed since."""
+    import hashlib
+    rec = SEARCH_TRAFFIC.get((workload, L))
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes"] if h.hexdigest()[:16] == rec["src"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -48,8 +69,10 @@ def parse():
     ap.add_argument("--search-only", action="store_true",
                     help="time only the search leg (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 256 MiB device copy (scale for HBM byte counters)")
+                    help="also run one plain elementwise add over 256 MiB (scale for the memory byte counters)")
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16/fp8, learned-entry and serving legs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-entry leg")
     ap.add_argument("--learn-n", type=int, default=1_000_000, help="base size of the vMF learned-entry leg")
     ap.add_argument("--learn-vmf", action="store_true", help="also run the learned entry on the vMF workload")
     ap.add_argument("--learn-train", type=int, default=200_000, help="training queries of the learned-entry leg")
@@ -142,6 +165,8 @@ def main():
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+
     def one_step():
         out = {}
         if not a.search_only:
@@ -159,12 +184,24 @@ def main():
             ev1.synchronize()
             times.append(ev0.elapsed_time(ev1))
         out["search_ms"] = float(np.median(times))
+        # the same launch after a 1 GiB write has evicted the index from the MALL
+        cold = []
+        for i in range(max(1, a.search_reps // 2)):
+            flush.fill_(float(i))
+            ev0.record(stream)
+            search(gb, L)
+            ev1.record(stream)
+            ev1.synchronize()
+            cold.append(ev0.elapsed_time(ev1))
+        out["search_ms_cold"] = float(np.median(cold))
         return out
 
     if a.copy_calibration:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        # a plain elementwise kernel of known traffic (reads and writes 256 MiB)
+        # to scale the memory counters
+        src = torch.zeros(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     for _ in range(a.warmup):
@@ -199,9 +236,17 @@ def main():
         "hops_mean": hops_alg / nq,
         "ndc_mean": ndc_alg / nq,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": search_traffic(cfg["name"], L) if n == cfg["n"] and nq == cfg["nq"]
+                     else None,
+                     "algorithmic_bytes": alg_bytes, "kernel": "search_kernel (float32)"},
         "sweep": sweep,
     }
+    cold_ms = float(np.median([s["search_ms_cold"] for s in steps]))
+    cold_gbs = alg_bytes / (cold_ms / 1e3) / 1e9
+    out["search_cold_mall"] = {"search_ms": round(cold_ms, 4), "qps": round(nq / (cold_ms / 1e3), 1),
+                               "achieved_GBs": round(cold_gbs, 1),
+                               "frac": round(cold_gbs / HBM_PEAK_GBS, 4)}
     if not a.search_only:
         bs = [s["build_s"] for s in steps]
         st = steps[-1]["stats"]
@@ -228,9 +273,12 @@ def main():
             forms[name] = quant_form(cng, torch, x, q, xd, qd, g, dt, gt_ids, gt_dk, k, cfg["L"],
                                      fp32_by_L, a.search_reps)
             print(f"# form {name} {forms[name]}", file=sys.stderr, flush=True)
-        forms["serving"] = serving_form(cng, torch, x, q, xd, g, gt_ids, a)
-        print(f"# serving {forms['serving']}", file=sys.stderr, flush=True)
-        forms["learned_entry"] = learned_form(cng, torch, a, 2, (x, q, xd, qd, g, gt_ids, gt_dk))
+        if not a.no_serving:
+            forms["serving"] = serving_form(cng, torch, x, q, xd, g, gt_ids, a)
+            print(f"# serving {forms['serving']}", file=sys.stderr, flush=True)
+        if not a.no_learned:
+            forms["learned_entry"] = learned_form(cng, torch, a, 2,
+                                                  (x, q, xd, qd, g, gt_ids, gt_dk))
         if a.learn_vmf:
             forms["learned_entry_vmf"] = learned_form(cng, torch, a, 4, None)
         out["forms"] = forms
