@@ -1,0 +1,109 @@
+"""Parity at full size: the 1M x 128 integer-valued (SIFT-shaped) workload with
+R = 32, C = 128, alpha = 1.2, searched with the 10k-query batch in the launch
+configuration the benchmark times.  The oracle checks sampled outputs one by one
+(candidate rows, pruned rows, search results) and the stages it can afford in
+full (entry point, connectivity on the GPU's pruned graph).
+
+Equality is bit for bit throughout (ids, adjacency, float32 distances)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2510_05975_amd as cng
+import workloads
+from gpu_util import dev, f32_of, host_ids, same_f32
+
+pytestmark = pytest.mark.gpu
+
+R, C, ALPHA, K = 32, 128, 1.2, 10
+
+
+@pytest.fixture(scope="module")
+def full():
+    print("fullscale: generate sift_like 1M x 128 + 10k queries", flush=True)
+    x, q = workloads.generate(2)
+    xd, qd = dev(x), dev(q)
+    print("fullscale: cng_build", flush=True)
+    g = cng.build(xd, R, C, ALPHA)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(20251007)
+    rows = np.unique(np.concatenate([[0, len(x) - 1], rng.integers(0, len(x), 30)]))
+    qs = np.unique(np.concatenate([[0, len(q) - 1], rng.integers(0, len(q), 190)]))
+    return dict(x=x, q=q, xd=xd, qd=qd, g=g, adj=host_ids(g.adj), rows=rows, qs=qs)
+
+
+def test_entry_point_full(full):
+    assert full["g"].entry == oracle.medoid(full["x"])
+
+
+def test_candidates_pruning_connectivity_full(full):
+    x, rows = full["x"], full["rows"]
+    n = len(x)
+    print("fullscale: cng_knn + cng_prune on all rows", flush=True)
+    ids_t, D_t, ovf = cng.knn(full["xd"], full["xd"], C, exclude_self=True)
+    pruned_t = cng.prune(full["xd"], ids_t, D_t, R, ALPHA, 0.0, width=R + 1)
+    torch.cuda.synchronize()
+    ids = host_ids(ids_t)
+    D = D_t.cpu().numpy()
+    pruned = host_ids(pruned_t)
+    del ids_t, D_t, pruned_t
+
+    # candidate rows: the first C of P \ {p} by (D, id), from C + 1 of P minus p
+    print(f"fullscale: oracle knn on {len(rows)} rows", flush=True)
+    oids, oD = oracle.knn(x[rows], x, C + 1)
+    for j, p in enumerate(rows):
+        keep = oids[j] != p
+        exp_ids, exp_D = oids[j][keep][:C], oD[j][keep][:C]
+        assert (ids[p] == exp_ids).all(), p
+        assert same_f32(D[p], f32_of(exp_D)), p
+
+    # pruned rows (Alg. 2 on the oracle's candidate lists of the sampled rows)
+    print("fullscale: oracle prune on the sampled rows", flush=True)
+    cand = np.full((n, C), oracle.NONE, np.uint32)
+    candD = np.full((n, C), np.inf)
+    for j, p in enumerate(rows):
+        keep = oids[j] != p
+        cand[p], candD[p] = oids[j][keep][:C], oD[j][keep][:C]
+    oadj = oracle.prune(x, cand, candD, R, ALPHA, 0.0, width=R + 1)
+    del cand, candD
+    assert (pruned[rows] == oadj[rows]).all()
+
+    # connectivity in full on the GPU's pruned graph, against the whole build
+    print("fullscale: oracle connect on the pruned graph", flush=True)
+    cadj, added, rounds = oracle.connect(x, pruned, full["g"].entry, C)
+    assert (full["adj"] == cadj).all()
+    assert full["g"].stats["connect_added"] == added
+    assert oracle.reachable(full["adj"], full["g"].entry).all()
+
+
+@pytest.mark.parametrize("L", [16, 96, 256])
+def test_search_sampled_full(full, L):
+    """Whole 10k batch in the benchmark's launch configuration (default visited
+    table), sampled queries against the oracle."""
+    ids_t, d_t, _, _ = cng.search(full["xd"], full["g"].adj, full["qd"], K, L, full["g"].entry)
+    _, _, hops_t, _ = cng.search(full["xd"], full["g"].adj, full["qd"], K, L, full["g"].entry,
+                                 stats=True)
+    torch.cuda.synchronize()
+    ids, dists, hops = host_ids(ids_t), d_t.cpu().numpy(), hops_t.cpu().numpy()
+    qs = full["qs"]
+    oids, od, ohops, _ = oracle.search(full["x"], full["adj"], full["q"][qs], K, L,
+                                       full["g"].entry)
+    assert (ids[qs] == oids).all()
+    assert same_f32(dists[qs], f32_of(od))
+    assert (hops[qs] == ohops).all()
+
+
+@pytest.mark.parametrize("dtype", [cng.BF16, cng.FP8])
+def test_search_quantized_sampled_full(full, dtype):
+    store = cng.quantize(full["xd"], dtype)
+    ids_t, d_t, _, _ = cng.search_quantized(full["xd"], store, full["g"].adj, full["qd"], K, 96,
+                                            full["g"].entry)
+    torch.cuda.synchronize()
+    ids, dists = host_ids(ids_t), d_t.cpu().numpy()
+    qs = full["qs"]
+    deq, _ = oracle.dequantized(full["x"], dtype)
+    oids, od, _, _ = oracle.search_rerank(deq, full["x"], full["adj"], full["q"][qs], K, 96,
+                                          full["g"].entry)
+    assert (ids[qs] == oids).all()
+    assert same_f32(dists[qs], f32_of(od))
