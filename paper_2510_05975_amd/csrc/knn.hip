@@ -368,15 +368,26 @@ struct FilterBf16Args {
     const uint16_t *cols16;  // [nc x K]
 };
 
+// LDS-only barrier: the band stores of the epilogue need not be complete here
+// (they are read only by compaction, which is preceded by a full barrier).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int KS>
-__global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void filter_bf16(FilterBf16Args A)
 {
     constexpr int K = 16 * KS;
     constexpr int BSTR = K + 8;  // bf16 elements per LDS column row (16 B pad: no bank conflicts)
     const FilterArgs &a = A.f;
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);              // 2 x BN2 x BSTR
-    float *thr = reinterpret_cast<float *>(Bs + 2 * BN2 * BSTR);    // BM2
+    float *nys = reinterpret_cast<float *>(Bs + 2 * BN2 * BSTR);    // 2 x BN2 column norms
+    float *thr = nys + 2 * BN2;                                     // BM2
     float *erow = thr + BM2;
     int *cnt = reinterpret_cast<int *>(erow + BM2);
     int *flag = cnt + BM2;                                          // [0]: a band needs compaction
@@ -388,6 +399,7 @@ __global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
     for (int li = threadIdx.x; li < BM2; li += 256) {
         int64_t gi = row0 + li;
         bool live = gi < rend;
+        // a dead row never takes a column: every F is finite or NaN
         thr[li] = live ? __builtin_inff() : -__builtin_inff();
         erow[li] = live ? a.E[gi] : 0.f;
         cnt[li] = 0;
@@ -408,10 +420,13 @@ __global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
         }
     }
 
-    // B tile loader: BN2 columns x K bf16 = BN2 * K / 8 chunks of 16 B
+    // B tile loader: BN2 columns x K bf16 = BN2 * K / 8 chunks of 16 B, plus the
+    // columns' squared norms (NaN past the last column: F is then NaN and never
+    // at or below a threshold)
     constexpr int CHUNKS = BN2 * K / 8;
     constexpr int PER_T = (CHUNKS + 255) / 256;
     uint4 pre[PER_T];
+    float pny = 0.f;
     auto fetch = [&](int64_t col0) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
@@ -421,6 +436,10 @@ __global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
             pre[i] = make_uint4(0, 0, 0, 0);
             if (c < CHUNKS && gj < a.nc)
                 pre[i] = *reinterpret_cast<const uint4 *>(A.cols16 + (size_t)gj * K + kc * 8);
+        }
+        if (threadIdx.x < BN2) {
+            const int64_t gj = col0 + threadIdx.x;
+            pny = gj < a.nc ? a.ny[gj] : __builtin_nanf("");
         }
     };
     auto stash = [&](int buf) {
@@ -432,6 +451,7 @@ __global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
                 *reinterpret_cast<uint4 *>(Bs + (size_t)buf * BN2 * BSTR + col * BSTR + kc * 8) = pre[i];
             }
         }
+        if (threadIdx.x < BN2) nys[buf * BN2 + threadIdx.x] = pny;
     };
 
     fetch(0);
@@ -459,38 +479,53 @@ __global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-        const uint16_t *Bb = Bs + (size_t)buf * BN2 * BSTR;
+        const uint16_t *Bb = Bs + (size_t)buf * BN2 * BSTR + (lane & 31) * BSTR + (lane >> 5) * 8;
+        // B fragments one k step ahead of the matrix instructions
+        bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bb);
+        bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bb + 32 * BSTR);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(
-                    Bb + (j * 32 + (lane & 31)) * BSTR + ks * 16 + (lane >> 5) * 8);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][ks], bfr, acc[i][j], 0, 0, 0);
+            bf16x8 n0 = b0, n1 = b1;
+            if (ks + 1 < KS) {
+                n0 = *reinterpret_cast<const bf16x8 *>(Bb + (ks + 1) * 16);
+                n1 = *reinterpret_cast<const bf16x8 *>(Bb + 32 * BSTR + (ks + 1) * 16);
             }
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], b0, acc[0][0], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], b0, acc[1][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], b1, acc[0][1], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], b1, acc[1][1], 0, 0, 0);
+            b0 = n0;
+            b1 = n1;
         }
-        // ---- epilogue: F = |y|^2 - 2 x.y against the row thresholds
+        // ---- epilogue: F = |y|^2 - 2 x.y against the row thresholds.  The
+        // compares of a 32 x 32 block are gathered into one wave mask first;
+        // appends (rare once the thresholds have settled) run only if it is set.
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int64_t gj = col0 + j * 32 + (lane & 31);
-            const bool colok = gj < a.nc;
-            const float nyj = colok ? a.ny[gj] : 0.f;
+            const float nyj = nys[buf * BN2 + j * 32 + (lane & 31)];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
+                float F[16];
+                uint64_t any = 0;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const float F = __builtin_fmaf(-2.0f, acc[i][j][r], nyj);
-                    bool take = colok && F <= th[i][r];
-                    if (__builtin_expect(ballot(take) != 0, 0) && take) {
-                        const int li = wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                        const int64_t gi = row0 + li;
-                        if (gi < rend && !(a.exclude_self && gi == gj)) {
-                            int pos = atomicAdd(&cnt[li], 1);
+                    F[r] = __builtin_fmaf(-2.0f, acc[i][j][r], nyj);
+                    any |= __builtin_amdgcn_ballot_w64(F[r] <= th[i][r]);
+                }
+                if (__builtin_expect(any != 0, 0)) {
+                    // 32-bit offsets: a pass holds at most 2^28 band entries
+                    const int lrow = wave * 64 + 4 * (lane >> 5);        // + i * 32 + (r's row)
+                    const int64_t gj = col0 + j * 32 + (lane & 31);
+                    const uint32_t jself = (uint32_t)(gj - row0);        // li of the column itself
+                    const uint32_t bbase = (uint32_t)(blockIdx.x * BM2 + lrow) * (uint32_t)a.CB;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int ro = i * 32 + 8 * (r >> 2) + (r & 3);
+                        if (F[r] <= th[i][r] && !(a.exclude_self && jself == (uint32_t)(lrow + ro))) {
+                            const int pos = atomicAdd(&cnt[lrow + ro], 1);
                             if (pos < a.CB) {
-                                const size_t o = (size_t)(gi - a.r0) * a.CB + pos;
-                                a.bandF[o] = F;
+                                const uint32_t o = bbase + (uint32_t)ro * (uint32_t)a.CB + (uint32_t)pos;
+                                a.bandF[o] = F[r];
                                 a.bandI[o] = (uint32_t)gj;
                             }
                             if (pos + 1 > a.CB - BN2) flag[0] = 1;
@@ -500,9 +535,10 @@ __global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
             }
         }
         if (more) stash(buf ^ 1);
-        __syncthreads();
+        lds_barrier();
         const bool last = !more;
         if (flag[0] || last) {
+            __syncthreads();  // band stores of every wave complete
             for (int li = wave; li < BM2; li += 4) {
                 const int c = cnt[li];
                 const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN2);
@@ -528,7 +564,7 @@ __global__ __launch_bounds__(256) void filter_bf16(FilterBf16Args A)
 
 size_t filter_bf16_lds_bytes(int K, int CB)
 {
-    size_t b = (size_t)2 * BN2 * (K + 8) * 2 + (size_t)BM2 * 4 * 3 + 8;
+    size_t b = (size_t)2 * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 + (size_t)BM2 * 4 * 3 + 8;
     b = (b + 15) & ~(size_t)15;
     return b + (size_t)4 * CB * 8;
 }
