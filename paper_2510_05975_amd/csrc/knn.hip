@@ -152,44 +152,118 @@ struct FilterLds {
     float *As, *Bs, *thr, *erow;
     int *cnt;
     uint64_t *sort;  // 4 x CB
+    uint32_t *hist;  // 4 x 256
 };
 
-// Compact the band of chunk row lr (one wave): sort it, set the threshold to
-// F_C + 2E and keep the entries at or below it.  A band that could not take
-// another tile of `bn` columns is marked overflowed (cnt = -1, threshold
-// -inf): that row is recomputed exhaustively.  After the last tile a band may
-// stay large (no further appends follow).
+// Compact the band of chunk row lr (one wave): find the C-th smallest F
+// exactly (radix select over the order-preserving 32-bit keys, 8 bits per
+// round), set the threshold to F_C + 2E and keep the entries at or below it
+// (in any order: the rerank sorts).  A band that could not take another tile
+// of `bn` columns is marked overflowed (cnt = -1, threshold -inf): that row is
+// recomputed exhaustively.  After the last tile a band may stay large (no
+// further appends follow).
 __device__ void compact_band(const FilterArgs &a, int64_t lr, float *thr_slot, int *cnt_slot,
-                             float erow, uint64_t *buf, bool last, int bn)
+                             float erow, uint32_t *keys, uint32_t *hist, bool last, int bn)
 {
     const int lane = lane_id();
     float *bF = a.bandF + (size_t)lr * a.CB;
     uint32_t *bI = a.bandI + (size_t)lr * a.CB;
     int c = *cnt_slot;
     if (c > a.CB) c = a.CB;
-    int np = 1;
-    while (np < c) np <<= 1;
-    for (int e = lane; e < np; e += 64)
-        buf[e] = e < c ? (((uint64_t)fkey(bF[e]) << 32) | bI[e]) : ~0ull;
-    wave_sort(buf, np);
     int keep = c;
     float thr = *thr_slot;
-    if (c >= a.C) {
-        float fc = unfkey((uint32_t)(buf[a.C - 1] >> 32));
-        thr = float_up((double)fc + 2.0 * (double)erow);
-        uint32_t tk = fkey(thr);
-        // entries are sorted: count those with F <= thr
-        int cntk = 0;
-        for (int e0 = 0; e0 < c; e0 += 64) {
-            int e = e0 + lane;
-            bool in = e < c && (uint32_t)(buf[e] >> 32) <= tk;
-            cntk += __popcll(ballot(in));
+    // the row's own column (appended by the bf16 filter of a self-join) gets
+    // the key ~0u: above every threshold, so it is never kept
+    const uint32_t self = a.exclude_self ? (uint32_t)(a.r0 + lr) : NONE;
+    int real = 0;
+    for (int e0 = 0; e0 < c; e0 += 64) {
+        const int e = e0 + lane;
+        bool ok = false;
+        if (e < c) {
+            ok = bI[e] != self;
+            keys[e] = ok ? fkey(bF[e]) : ~0u;
         }
-        keep = cntk;
+        real += __popcll(ballot(ok));
     }
-    for (int e = lane; e < keep; e += 64) {
-        bF[e] = unfkey((uint32_t)(buf[e] >> 32));
-        bI[e] = (uint32_t)buf[e];
+    if (real < c && real < a.C) {
+        // too few to cut: drop the row's own column only
+        int out = 0;
+        for (int e0 = 0; e0 < c; e0 += 64) {
+            const int e = e0 + lane;
+            const bool in = e < c && keys[e] != ~0u;
+            const uint32_t id = in ? bI[e] : 0u;
+            const uint64_t bm = ballot(in);
+            const int p = out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+            if (in) {
+                bF[p] = unfkey(keys[e]);
+                bI[p] = id;
+            }
+            out += __popcll(bm);
+        }
+        keep = out;
+    } else if (c >= a.C) {
+        uint32_t prefix = 0, pmask = 0;
+        uint32_t k = (uint32_t)a.C;  // rank (1-based) among the keys matching the prefix
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (int b = lane; b < 256; b += 64) hist[b] = 0;
+            wave_sync();
+            for (int e = lane; e < c; e += 64) {
+                const uint32_t kk = keys[e];
+                if ((kk & pmask) == prefix) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
+            }
+            wave_sync();
+            // lane l holds buckets 4l .. 4l+3; inclusive scan of their sums
+            const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
+                           h3 = hist[4 * lane + 3];
+            const uint32_t s = h0 + h1 + h2 + h3;
+            uint32_t incl = s;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            const uint32_t excl = incl - s;
+            const uint64_t m = ballot(excl < k && k <= incl);
+            const int L = __builtin_ctzll(m);
+            uint32_t before = excl;
+            int b = 4 * lane;
+            if (before + h0 < k) {
+                before += h0;
+                ++b;
+                if (before + h1 < k) {
+                    before += h1;
+                    ++b;
+                    if (before + h2 < k) {
+                        before += h2;
+                        ++b;
+                    }
+                }
+            }
+            b = __builtin_amdgcn_readlane(b, L);
+            before = (uint32_t)__builtin_amdgcn_readlane((int)before, L);
+            k -= before;
+            prefix |= (uint32_t)b << shift;
+            pmask |= 255u << shift;
+            wave_sync();
+        }
+        thr = float_up((double)unfkey(prefix) + 2.0 * (double)erow);
+        const uint32_t tk = fkey(thr);
+        // keep entries with key <= tk, in place (writes never pass the reads)
+        int out = 0;
+        for (int e0 = 0; e0 < c; e0 += 64) {
+            const int e = e0 + lane;
+            const bool in = e < c && keys[e] <= tk;
+            const uint32_t id = in ? bI[e] : 0u;
+            const uint64_t bm = ballot(in);
+            const int p = out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+            if (in) {
+                bF[p] = unfkey(keys[e]);
+                bI[p] = id;
+            }
+            out += __popcll(bm);
+        }
+        keep = out;
     }
     wave_sync();
     if (lane == 0) {
@@ -243,6 +317,7 @@ __global__ __launch_bounds__(NT) void filter_f32(FilterArgs a)
     s.cnt = reinterpret_cast<int *>(s.erow + BM);
     s.sort = reinterpret_cast<uint64_t *>(s.cnt + BM + 2);  // +2 keeps 8-byte alignment slack
     s.sort = reinterpret_cast<uint64_t *>(((uintptr_t)s.sort + 7) & ~(uintptr_t)7);
+    s.hist = reinterpret_cast<uint32_t *>(s.sort + (size_t)(NT / 64) * a.CB);
 
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int wr = wave >> 1, wc = wave & 1;
@@ -321,7 +396,8 @@ __global__ __launch_bounds__(NT) void filter_f32(FilterArgs a)
             const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN);
             if (need)
                 compact_band(a, (int64_t)blockIdx.x * BM + li, &s.thr[li], &s.cnt[li], s.erow[li],
-                             s.sort + (size_t)wave * a.CB, last, BN);
+                             reinterpret_cast<uint32_t *>(s.sort + (size_t)wave * a.CB),
+                             s.hist + wave * 256, last, BN);
         }
         __syncthreads();
     }
@@ -341,6 +417,7 @@ __global__ __launch_bounds__(NT) void filter_f32(FilterArgs a)
 // A workgroup owns 256 rows (64 per wave, kept in registers as MFMA A
 // fragments) and sweeps column tiles of 64 through double-buffered LDS.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM2 = 256, BN2 = 64;
 
@@ -389,9 +466,10 @@ void filter_bf16(FilterBf16Args A)
     float *nys = reinterpret_cast<float *>(Bs + 2 * BN2 * BSTR);    // 2 x BN2 column norms
     float *thr = nys + 2 * BN2;                                     // BM2
     float *erow = thr + BM2;
-    int *cnt = reinterpret_cast<int *>(erow + BM2);
+    int *cnt = reinterpret_cast<int *>(erow + BM2);                // band counts, during compaction
     int *flag = cnt + BM2;                                          // [0]: a band needs compaction
-    uint64_t *sortb = reinterpret_cast<uint64_t *>(flag + 2);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(flag + 4);        // 4 x 256
+    uint32_t *keys = hist + 4 * 256;                                // 4 x CB
 
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM2;
@@ -405,6 +483,12 @@ void filter_bf16(FilterBf16Args A)
         cnt[li] = 0;
     }
     if (threadIdx.x == 0) flag[0] = 0;
+    // Next free band slot of row wave * 64 + lane, as an offset into the band
+    // arrays (a pass holds at most 2^28 entries).  A wave alone appends to its
+    // 64 rows, so these live in a register, read and written per row by lane
+    // index, and go through LDS (as counts) only around compactions.
+    const uint32_t rowstart = (uint32_t)(blockIdx.x * BM2 + wave * 64 + lane) * (uint32_t)a.CB;
+    uint32_t mypos = rowstart;
 
     // A fragments of this wave's 64 rows: [row block][k step]
     bf16x8 af[2][KS];
@@ -424,34 +508,37 @@ void filter_bf16(FilterBf16Args A)
     // columns' squared norms (NaN past the last column: F is then NaN and never
     // at or below a threshold)
     constexpr int CHUNKS = BN2 * K / 8;
-    constexpr int PER_T = (CHUNKS + 255) / 256;
-    uint4 pre[PER_T];
+    static_assert(CHUNKS % 256 == 0, "K is padded to a multiple of 32");
+    constexpr int PER_T = CHUNKS / 256;
+    // Loads are unconditional (columns past the end are clamped to the last
+    // one; their F is NaN through the norm), so no register is cleared while
+    // a load may be in flight.
+    u32x4 pre[PER_T];
     float pny = 0.f;
+    bool pdead = false;
     auto fetch = [&](int64_t col0) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
-            int c = threadIdx.x + 256 * i;
-            int col = c / (K / 8), kc = c % (K / 8);
+            const int c = threadIdx.x + 256 * i;
+            const int col = c / (K / 8), kc = c % (K / 8);
             int64_t gj = col0 + col;
-            pre[i] = make_uint4(0, 0, 0, 0);
-            if (c < CHUNKS && gj < a.nc)
-                pre[i] = *reinterpret_cast<const uint4 *>(A.cols16 + (size_t)gj * K + kc * 8);
+            gj = gj < a.nc ? gj : a.nc - 1;
+            pre[i] = *reinterpret_cast<const u32x4 *>(A.cols16 + (size_t)gj * K + kc * 8);
         }
         if (threadIdx.x < BN2) {
             const int64_t gj = col0 + threadIdx.x;
-            pny = gj < a.nc ? a.ny[gj] : __builtin_nanf("");
+            pdead = gj >= a.nc;
+            pny = a.ny[pdead ? a.nc - 1 : gj];
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
-            int c = threadIdx.x + 256 * i;
-            if (c < CHUNKS) {
-                int col = c / (K / 8), kc = c % (K / 8);
-                *reinterpret_cast<uint4 *>(Bs + (size_t)buf * BN2 * BSTR + col * BSTR + kc * 8) = pre[i];
-            }
+            const int c = threadIdx.x + 256 * i;
+            const int col = c / (K / 8), kc = c % (K / 8);
+            *reinterpret_cast<u32x4 *>(Bs + (size_t)buf * BN2 * BSTR + col * BSTR + kc * 8) = pre[i];
         }
-        if (threadIdx.x < BN2) nys[buf * BN2 + threadIdx.x] = pny;
+        if (threadIdx.x < BN2) nys[buf * BN2 + threadIdx.x] = pdead ? __builtin_nanf("") : pny;
     };
 
     fetch(0);
@@ -497,57 +584,71 @@ void filter_bf16(FilterBf16Args A)
             b0 = n0;
             b1 = n1;
         }
-        // ---- epilogue: F = |y|^2 - 2 x.y against the row thresholds.  The
-        // compares of a 32 x 32 block are gathered into one wave mask first;
-        // appends (rare once the thresholds have settled) run only if it is set.
+        // next tile into the other buffer now: its loads were issued a whole
+        // matrix phase ago, and waiting for them later would also wait for the
+        // band stores of the epilogue
+        if (more) stash(buf ^ 1);
+        // ---- epilogue: F = |y|^2 - 2 x.y against the row thresholds.  One
+        // compare per element gives a wave mask per (row pair, column block);
+        // appends (rare once the thresholds have settled) take positions from
+        // the register counts: a popcount per row and a prefix count per lane.
+        // A row's own column (self-joins) is appended like any other and
+        // dropped by the compaction and the rerank.
+        bool wflag = false;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const float nyj = nys[buf * BN2 + j * 32 + (lane & 31)];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                float F[16];
-                uint64_t any = 0;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    F[r] = __builtin_fmaf(-2.0f, acc[i][j][r], nyj);
-                    any |= __builtin_amdgcn_ballot_w64(F[r] <= th[i][r]);
-                }
-                if (__builtin_expect(any != 0, 0)) {
-                    // 32-bit offsets: a pass holds at most 2^28 band entries
-                    const int lrow = wave * 64 + 4 * (lane >> 5);        // + i * 32 + (r's row)
-                    const int64_t gj = col0 + j * 32 + (lane & 31);
-                    const uint32_t jself = (uint32_t)(gj - row0);        // li of the column itself
-                    const uint32_t bbase = (uint32_t)(blockIdx.x * BM2 + lrow) * (uint32_t)a.CB;
+                    const float F = __builtin_fmaf(-2.0f, acc[i][j][r], nyj);
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(F <= th[i][r]);
+                    if (__builtin_expect(m != 0, 0)) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int ro = i * 32 + 8 * (r >> 2) + (r & 3);
-                        if (F[r] <= th[i][r] && !(a.exclude_self && jself == (uint32_t)(lrow + ro))) {
-                            const int pos = atomicAdd(&cnt[lrow + ro], 1);
-                            if (pos < a.CB) {
-                                const uint32_t o = bbase + (uint32_t)ro * (uint32_t)a.CB + (uint32_t)pos;
-                                a.bandF[o] = F[r];
-                                a.bandI[o] = (uint32_t)gj;
+                        for (int h = 0; h < 2; ++h) {
+                            // lanes 32h .. 32h+31 hold row ro of this wave
+                            const int ro = i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                            const uint64_t hm = m & (h ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull);
+                            if (hm) {
+                                // a row holds at most CB - BN2 entries when a tile
+                                // starts and takes at most BN2 in it: every slot
+                                // taken here is below CB
+                                const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)mypos, ro);
+                                const uint32_t o = base + __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(hm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+                                if ((hm >> lane) & 1ull) {
+                                    a.bandF[o] = F;
+                                    a.bandI[o] = (uint32_t)(col0 + j * 32 + (lane & 31));
+                                }
+                                const uint32_t nb = base + (uint32_t)__popcll(hm);
+                                wflag |= (int)(base & (uint32_t)(a.CB - 1)) + __popcll(hm) > a.CB - BN2;
+                                asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mypos) : "s"(nb), "i"(ro));
                             }
-                            if (pos + 1 > a.CB - BN2) flag[0] = 1;
                         }
                     }
                 }
             }
         }
-        if (more) stash(buf ^ 1);
+        if (wflag && lane == 0) flag[0] = 1;
         lds_barrier();
         const bool last = !more;
         if (flag[0] || last) {
-            __syncthreads();  // band stores of every wave complete
+            cnt[wave * 64 + lane] = (int)(mypos - rowstart);
+            __syncthreads();  // band stores and counts of every wave complete
             for (int li = wave; li < BM2; li += 4) {
                 const int c = cnt[li];
                 const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN2);
                 if (need)
                     compact_band(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
-                                 sortb + (size_t)wave * a.CB, last, BN2);
+                                 keys + (size_t)wave * a.CB, hist + wave * 256, last, BN2);
             }
             __syncthreads();
             if (threadIdx.x == 0) flag[0] = 0;
+            {
+                const int c = cnt[wave * 64 + lane];  // -1: overflowed, takes nothing more
+                mypos = rowstart + (uint32_t)(c > 0 ? c : 0);
+            }
             load_thr();
             __syncthreads();
         }
@@ -564,9 +665,8 @@ void filter_bf16(FilterBf16Args A)
 
 size_t filter_bf16_lds_bytes(int K, int CB)
 {
-    size_t b = (size_t)2 * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 + (size_t)BM2 * 4 * 3 + 8;
-    b = (b + 15) & ~(size_t)15;
-    return b + (size_t)4 * CB * 8;
+    return (size_t)2 * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 + (size_t)BM2 * 4 * 3 + 16 +
+           (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
 }
 
 // ---------------------------------------------------------------- rerank
@@ -581,6 +681,7 @@ struct RerankArgs {
     const int *cnt;
     uint32_t *ids;  // [nr x C]
     float *D;
+    int exclude_self;  // self-join: a band may hold the row's own column
 };
 
 template <int G, int RND, bool VEC>
@@ -601,12 +702,15 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a)
 #pragma unroll
     for (int r = 0; r < RND; ++r) xr[r] = load_chunk<VEC>(x, a.d, r, gl);
     const uint32_t *bI = a.bandI + (size_t)lr * a.CB;
+    const uint32_t self = a.exclude_self ? (uint32_t)gi : NONE;
+    int nself = 0;
     for (int b = 0; b < c; b += NG) {
         const int e = b + grp;
         float4 yr[RND];
         uint32_t id = NONE;
         if (e < c) {
             id = bI[e];
+            if (id == self) id = 0;  // its key is replaced below
             const float *y = a.cols + (size_t)id * a.d;
 #pragma unroll
             for (int r = 0; r < RND; ++r) yr[r] = load_chunk<VEC>(y, a.d, r, gl);
@@ -618,7 +722,9 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a)
 #pragma unroll
         for (int r = 0; r < RND; ++r) acc = chunk_fma(xr[r], yr[r], acc);
         acc = group_sum<G>(acc);
-        if (gl == 0 && e < c) buf[e] = make_key(acc, id);
+        const bool is_self = e < c && bI[e] == self;
+        nself += __popcll(ballot(gl == 0 && is_self));
+        if (gl == 0 && e < c) buf[e] = is_self ? ~0ull : make_key(acc, id);
     }
     int np = 1;
     while (np < c) np <<= 1;
@@ -626,10 +732,11 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a)
     for (int e = c + lane; e < np; e += 64) buf[e] = ~0ull;
     wave_sync();
     wave_sort(buf, np);
+    const int cv = c - nself;  // the row's own column sorted last
     for (int e = lane; e < a.C; e += 64) {
         uint32_t id = NONE;
         float dd = __builtin_inff();
-        if (e < c) {
+        if (e < cv) {
             id = key_id(buf[e]);
             dd = key_dist(buf[e]);
         }
@@ -758,7 +865,7 @@ size_t filter_lds_bytes(int CB)
 {
     size_t b = (size_t)BK * (BM + APAD) * 4 * 2 + (size_t)BM * 4 * 2 + (size_t)(BM + 2) * 4;
     b = (b + 15) & ~(size_t)15;
-    return b + (size_t)(NT / 64) * CB * 8;
+    return b + (size_t)(NT / 64) * CB * 8 + (size_t)(NT / 64) * 256 * 4;
 }
 
 }  // namespace
@@ -780,7 +887,7 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
     p.bytes = align256((size_t)nc * 4) + align256((size_t)nr * 4) * 2 + align256(sizeof(PrepOut)) +
               align256((size_t)chunk * CB * 4) * 2 + align256((size_t)chunk * 4);
     if (d <= 128) {  // bf16 copies for the exact small-integer filter
-        const int K = (d + 15) / 16 * 16;
+        const int K = (d + 31) / 32 * 32;
         p.bytes += align256((size_t)nc * K * 2) + align256((size_t)nr * K * 2);
     }
     return p;
@@ -806,7 +913,7 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     w += align256((size_t)plan.chunk_rows * CB * 4);
     int *cnt = (int *)w;
     w += align256((size_t)plan.chunk_rows * 4);
-    const int K16 = (d + 15) / 16 * 16;
+    const int K16 = (d + 31) / 32 * 32;  // bf16 row length: whole k steps of 16, an even count
     uint16_t *cols16 = nullptr, *rows16 = nullptr;
     if (d <= 128) {
         cols16 = (uint16_t *)w;
@@ -861,14 +968,10 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
             FilterBf16Args fb{fa, rows16, cols16};
             const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
             const unsigned lds = (unsigned)filter_bf16_lds_bytes(K16, CB);
-            switch (K16 / 16) {
-            case 1: hipLaunchKernelGGL(filter_bf16<1>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 2: hipLaunchKernelGGL(filter_bf16<2>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 3: hipLaunchKernelGGL(filter_bf16<3>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 4: hipLaunchKernelGGL(filter_bf16<4>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 5: hipLaunchKernelGGL(filter_bf16<5>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 6: hipLaunchKernelGGL(filter_bf16<6>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 7: hipLaunchKernelGGL(filter_bf16<7>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            switch (K16 / 32) {
+            case 1: hipLaunchKernelGGL(filter_bf16<2>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 2: hipLaunchKernelGGL(filter_bf16<4>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            case 3: hipLaunchKernelGGL(filter_bf16<6>, dim3(blocks), dim3(256), lds, stream, fb); break;
             default: hipLaunchKernelGGL(filter_bf16<8>, dim3(blocks), dim3(256), lds, stream, fb); break;
             }
         } else {
@@ -876,7 +979,7 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
             if (vec) hipLaunchKernelGGL(filter_f32<true>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
             else hipLaunchKernelGGL(filter_f32<false>, dim3(fblocks), dim3(NT), (unsigned)flds, stream, fa);
         }
-        RerankArgs ra{rows, r0, chunk, nr, cols, nc, d, C, CB, bandF, bandI, cnt, ids, D};
+        RerankArgs ra{rows, r0, chunk, nr, cols, nc, d, C, CB, bandF, bandI, cnt, ids, D, exclude_self};
         const unsigned rblocks = (unsigned)((chunk + 3) / 4);
         hipLaunchKernelGGL(rfn, dim3(rblocks), dim3(256), (unsigned)(4 * CB * 8), stream, ra);
         const int CBX = next_pow2(2 * C + 64 > CB ? 2 * C + 64 : CB);
