@@ -66,8 +66,10 @@ def lib():
         L.orc_connect.argtypes = [f32p, i64, C.c_int, u32p, C.c_int, C.c_uint32, C.c_int, C.c_int,
                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.orc_build.argtypes = [f32p, i64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
-                                C.c_double, C.c_int, C.c_int, C.c_int, u32p,
+                                C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, u32p,
                                 C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
+        L.orc_backward.argtypes = [f32p, i64, C.c_int, u32p, C.c_int, C.c_int, C.c_int,
+                                   C.c_double, C.c_double, C.c_int]
         L.orc_round_bf16.restype = C.c_float
         L.orc_round_bf16.argtypes = [C.c_float]
         L.orc_round_e4m3.restype = C.c_float
@@ -182,16 +184,26 @@ def connect(points, adj, entry: int, Lc: int, mode: int = FP32):
     return adj, added.value, rounds.value
 
 
+def backward(points, adj, R: int, Cb: int, alpha: float, tau: float = 0.0, mode: int = FP32):
+    """Alg. 3 phase 3 (backward edges, lazy pruning) on a copy of ``adj``."""
+    points = _f32(points)
+    n, d = points.shape
+    adj = np.array(adj, np.uint32, copy=True, order="C")
+    _check(lib().orc_backward(points, n, d, adj, R, adj.shape[1], Cb, alpha, tau, mode),
+           "backward")
+    return adj
+
+
 def build(points, R: int, C_: int, alpha: float, tau: float = 0.0, mode: int = FP32,
-          connect: bool = True, Lc: int = 0, extra: int = 1):
+          connect: bool = True, Lc: int = 0, extra: int = 1, backward: bool = False):
     """Whole fixed-alpha build -> (adj (n x (R + extra)), entry, n_added)."""
     points = _f32(points)
     n, d = points.shape
     adj = np.empty((n, R + extra), np.uint32)
     entry = C.c_uint32(0)
     added = C.c_int64(0)
-    _check(lib().orc_build(points, n, d, R, extra, C_, alpha, tau, mode, int(connect), Lc, adj,
-                           C.byref(entry), C.byref(added)), "build")
+    _check(lib().orc_build(points, n, d, R, extra, C_, alpha, tau, mode, int(connect),
+                           int(backward), Lc, adj, C.byref(entry), C.byref(added)), "build")
     return adj, int(entry.value), added.value
 
 

@@ -211,6 +211,21 @@ static int orc_prunes(const float *pts, int d, uint32_t p, uint32_t u, uint32_t 
     return a > rhs;
 }
 
+/* Alg. 2 on one candidate list V (ascending by (D, id)): keep u unless an
+ * earlier kept v prunes it, stopping once R are kept.  Returns the count. */
+static int prune_sorted(const float *pts, int d, uint32_t p, const orc_key *V, int nv, int R,
+                        double alpha, double tau, int mode, uint32_t *S)
+{
+    int ns = 0;
+    for (int j = 0; j < nv && ns < R; ++j) {
+        int pruned = 0;
+        for (int s = 0; s < ns && !pruned; ++s)
+            pruned = orc_prunes(pts, d, p, V[j].id, S[s], V[j].D, alpha, tau, mode);
+        if (!pruned) S[ns++] = V[j].id;
+    }
+    return ns;
+}
+
 /* Alg. 2 pruning(p, V, alpha) on the candidate list of every point, keeping at
  * most R out-neighbours, written into rows of width W >= R (padded with
  * ORC_NONE; slots beyond R are spare slots for connectivity edges).  Stopping once R are kept equals returning the R
@@ -243,19 +258,116 @@ int orc_prune(const float *pts, int64_t n, int d, const uint32_t *cand, const do
                 ++nv;
             }
             qsort(V, (size_t)nv, sizeof(orc_key), cmp_key);
-            int ns = 0;
-            for (int j = 0; j < nv && ns < R; ++j) {
-                int pruned = 0;
-                for (int s = 0; s < ns && !pruned; ++s)
-                    pruned = orc_prunes(pts, d, (uint32_t)p, V[j].id, S[s], V[j].D, alpha, tau, mode);
-                if (!pruned) S[ns++] = V[j].id;
-            }
+            int ns = prune_sorted(pts, d, (uint32_t)p, V, nv, R, alpha, tau, mode, S);
             for (int s = 0; s < W; ++s) adj[(size_t)p * W + s] = s < ns ? S[s] : ORC_NONE;
         }
         free(V);
         free(S);
     }
     return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Alg. 3 phase 3: backward edges with lazy pruning (Section 4.3).  For every  */
+/* edge (u, v) of the pruned graph the reverse edge (v, u) is added.  Each      */
+/* point's candidate set V is its out-neighbours together with the sources of  */
+/* the edges into it (a set), ordered by (D, id).  The paper bounds candidate  */
+/* sets by C; here V is cut to its Cb nearest.  A point with |V| > R is pruned  */
+/* once over V (Alg. 2, cap R); otherwise V itself becomes its row (in (D, id)  */
+/* order; the order of a row does not change Alg. 1).  Every decision reads    */
+/* the graph as it was before this phase.  Rows have width W >= R.             */
+/* ------------------------------------------------------------------------- */
+int orc_backward(const float *pts, int64_t n, int d, uint32_t *adj, int R, int W, int Cb,
+                 double alpha, double tau, int mode)
+{
+    if (n < 1 || d < 1 || R < 1 || W < R || Cb < 1 || !(alpha > 0.0) || !(tau >= 0.0))
+        return ORC_EINVAL;
+    int64_t *off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    uint32_t *out = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * W);
+    uint32_t *src = NULL;
+    int rc = ORC_OK;
+    if (!off || !cur || !out) { rc = ORC_ENOMEM; goto done; }
+    /* sources of the edges into every point, in increasing source order */
+    for (int64_t u = 0; u < n; ++u)
+        for (int s = 0; s < W; ++s) {
+            uint32_t v = adj[(size_t)u * W + s];
+            if (v == ORC_NONE || (int64_t)v >= n) break;
+            off[v + 1]++;
+        }
+    for (int64_t v = 0; v < n; ++v) off[v + 1] += off[v];
+    src = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(off[n] > 0 ? off[n] : 1));
+    if (!src) { rc = ORC_ENOMEM; goto done; }
+    for (int64_t v = 0; v < n; ++v) cur[v] = off[v];
+    for (int64_t u = 0; u < n; ++u)
+        for (int s = 0; s < W; ++s) {
+            uint32_t v = adj[(size_t)u * W + s];
+            if (v == ORC_NONE || (int64_t)v >= n) break;
+            src[cur[v]++] = (uint32_t)u;
+        }
+    int fail = 0;
+#pragma omp parallel
+    {
+        int64_t cap = 0;
+        orc_key *V = NULL;
+        uint32_t *S = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)R);
+        if (!S) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < n; ++p) {
+            if (!S) continue;
+            int64_t need = W + (off[p + 1] - off[p]);
+            if (need > cap) {
+                free(V);
+                cap = need;
+                V = (orc_key *)malloc(sizeof(orc_key) * (size_t)cap);
+                if (!V) {
+                    cap = 0;
+#pragma omp atomic write
+                    fail = 1;
+                    continue;
+                }
+            }
+            const float *xp = pts + (size_t)p * d;
+            int64_t nv = 0;
+            for (int s = 0; s < W; ++s) {
+                uint32_t v = adj[(size_t)p * W + s];
+                if (v == ORC_NONE || (int64_t)v >= n) break;
+                V[nv].id = v;
+                V[nv].D = dist_mode(xp, pts + (size_t)v * d, d, mode);
+                ++nv;
+            }
+            for (int64_t e = off[p]; e < off[p + 1]; ++e) {
+                V[nv].id = src[e];
+                V[nv].D = dist_mode(xp, pts + (size_t)src[e] * d, d, mode);
+                ++nv;
+            }
+            qsort(V, (size_t)nv, sizeof(orc_key), cmp_key);
+            /* a set: an id seen twice (u -> p and p -> u) has equal keys, adjacent */
+            int64_t m = 0;
+            for (int64_t j = 0; j < nv; ++j)
+                if (m == 0 || V[j].id != V[m - 1].id) V[m++] = V[j];
+            if (m > Cb) m = Cb;
+            uint32_t *row = out + (size_t)p * W;
+            int ns;
+            if (m <= R) {
+                for (int64_t j = 0; j < m; ++j) S[j] = V[j].id;
+                ns = (int)m;
+            } else {
+                ns = prune_sorted(pts, d, (uint32_t)p, V, (int)m, R, alpha, tau, mode, S);
+            }
+            for (int s = 0; s < W; ++s) row[s] = s < ns ? S[s] : ORC_NONE;
+        }
+        free(V);
+        free(S);
+    }
+    if (fail) { rc = ORC_ENOMEM; goto done; }
+    memcpy(adj, out, sizeof(uint32_t) * (size_t)n * W);
+done:
+    free(off); free(cur); free(out); free(src);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -703,11 +815,13 @@ done:
 
 /* ------------------------------------------------------------------------- */
 /* Whole build with a fixed alpha: entry point, exact candidates, pruning of    */
-/* each candidate list (Alg. 2 with cap R), then connectivity.  Rows have      */
-/* width R + extra; the extra slots only ever hold connectivity edges.          */
+/* each candidate list (Alg. 2 with cap R), optionally backward edges with     */
+/* lazy pruning (phase 3), then connectivity.  Rows have width R + extra; the  */
+/* extra slots only ever hold connectivity edges.                               */
 /* ------------------------------------------------------------------------- */
 int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, double alpha, double tau,
-              int mode, int connect, int Lc, uint32_t *adj, uint32_t *entry, int64_t *n_added)
+              int mode, int connect, int backward, int Lc, uint32_t *adj, uint32_t *entry,
+              int64_t *n_added)
 {
     if (n < 2 || d < 1 || R < 1 || extra < 0 || C < 1) return ORC_EINVAL;
     int W = R + extra;
@@ -720,6 +834,8 @@ int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, doubl
     rc = orc_knn(pts, n, pts, n, d, Ce, 1, mode, cand, cD);
     if (rc) goto out;
     rc = orc_prune(pts, n, d, cand, cD, Ce, R, W, alpha, tau, mode, adj);
+    if (rc) goto out;
+    if (backward) rc = orc_backward(pts, n, d, adj, R, W, Ce, alpha, tau, mode);
     if (rc) goto out;
     if (n_added) *n_added = 0;
     if (connect) rc = orc_connect(pts, n, d, adj, W, *entry, Lc > 0 ? Lc : Ce, mode, n_added, NULL);

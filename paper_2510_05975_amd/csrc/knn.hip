@@ -488,6 +488,9 @@ void filter_bf16(FilterBf16Args A)
     // 64 rows, so these live in a register, read and written per row by lane
     // index, and go through LDS (as counts) only around compactions.
     const uint32_t rowstart = (uint32_t)(blockIdx.x * BM2 + wave * 64 + lane) * (uint32_t)a.CB;
+    // compaction once a band could not take another whole tile (measured: an
+    // earlier cut, at half the capacity, costs more than the appends it saves)
+    const int trig = a.CB - BN2;
     uint32_t mypos = rowstart;
 
     // A fragments of this wave's 64 rows: [row block][k step]
@@ -622,7 +625,7 @@ void filter_bf16(FilterBf16Args A)
                                     a.bandI[o] = (uint32_t)(col0 + j * 32 + (lane & 31));
                                 }
                                 const uint32_t nb = base + (uint32_t)__popcll(hm);
-                                wflag |= (int)(base & (uint32_t)(a.CB - 1)) + __popcll(hm) > a.CB - BN2;
+                                wflag |= (int)(base & (uint32_t)(a.CB - 1)) + __popcll(hm) > trig;
                                 asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mypos) : "s"(nb), "i"(ro));
                             }
                         }
@@ -638,7 +641,7 @@ void filter_bf16(FilterBf16Args A)
             __syncthreads();  // band stores and counts of every wave complete
             for (int li = wave; li < BM2; li += 4) {
                 const int c = cnt[li];
-                const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN2);
+                const bool need = c >= 0 && (last ? c > a.C : c > trig);
                 if (need)
                     compact_band(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
                                  keys + (size_t)wave * a.CB, hist + wave * 256, last, BN2);
