@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain elementwise add over 256 MiB (scale for the memory byte counters)")
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16/fp8, learned-entry and serving legs")
+    ap.add_argument("--backward", action="store_true",
+                    help="build with backward edges and lazy pruning (Algorithm 3, phase 3)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-entry leg")
     ap.add_argument("--learn-n", type=int, default=1_000_000, help="base size of the vMF learned-entry leg")
@@ -125,7 +127,7 @@ def main():
     print(f"# ground truth in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
 
     def build():
-        return cng.build(xd, R, Cc, alpha, tau)
+        return cng.build(xd, R, Cc, alpha, tau, backward=a.backward)
 
     def search(g, L, vlog2=a.visited_log2, stats=False):
         return cng.search(xd, g.adj, qd, k, L, g.entry, visited_log2=vlog2, stats=stats)
@@ -229,7 +231,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "n": n, "d": d, "nq": nq, "R": R, "C": Cc,
-                   "alpha": alpha, "tau": tau, "k": k, "L": L, "row_width": W},
+                   "alpha": alpha, "tau": tau, "k": k, "L": L, "row_width": W,
+                   "backward_edges": bool(a.backward)},
         "recall@10": chosen["recall_tie"],
         "recall@10_strict": chosen["recall_strict"],
         "search_ms": round(search_ms, 4),
@@ -256,7 +259,8 @@ def main():
         peak = BF16_MFMA_TFLOPS if st.get("filter_dtype") == 1 else FP32_MFMA_TFLOPS
         out["build_secs"] = round(float(np.median(bs)), 4)
         out["build_stages_ms"] = {kk: round(st[kk], 2) for kk in
-                                  ("ms_entry", "ms_candidates", "ms_prune", "ms_connect")}
+                                  ("ms_entry", "ms_candidates", "ms_prune", "ms_backward",
+                                   "ms_connect")}
         out["build_info"] = {kk: st[kk] for kk in ("connect_rounds", "connect_added",
                                                     "overflow_rows", "exact_integer",
                                                     "filter_dtype")}
@@ -421,7 +425,7 @@ def learned_form(cng, torch, a, cfg_id, prepared):
         x, q = workloads.generate(cfg_id, n=n, nq=nq)
         xd, qd = (torch.from_numpy(v).to("cuda:0") for v in (x, q))
         t0 = time.perf_counter()
-        g = cng.build(xd, cfg["R"], cfg["C"], cfg["alpha"], cfg["tau"])
+        g = cng.build(xd, cfg["R"], cfg["C"], cfg["alpha"], cfg["tau"], backward=a.backward)
         torch.cuda.synchronize()
         build_s = time.perf_counter() - t0
         gt_t, gD, _ = cng.knn(qd, xd, k)

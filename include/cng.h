@@ -50,7 +50,8 @@ typedef enum {
 #define CNG_NONE 0xFFFFFFFFu
 
 /* Build flags */
-#define CNG_BUILD_CONNECT 1u /* run the connectivity phase (Algorithm 3, phase 4) */
+#define CNG_BUILD_CONNECT 1u  /* run the connectivity phase (Algorithm 3, phase 4) */
+#define CNG_BUILD_BACKWARD 2u /* backward edges with lazy pruning (Algorithm 3, phase 3) */
 
 typedef struct {
     int32_t R;           /* out-degree cap of pruning (Algorithm 2 keeps at most R), >= 1 */
@@ -71,6 +72,7 @@ typedef struct {
     int64_t overflow_rows;     /* candidate rows recomputed exhaustively (filter band full) */
     int32_t exact_integer;     /* 1 if the filter ran in exact small-integer mode */
     int32_t filter_dtype;      /* 0 = fp32 MFMA filter, 1 = bf16 MFMA filter */
+    double ms_backward;        /* wall time of the backward-edge phase (0 if not run) */
 } cng_build_stats;
 
 /* ------------------------------------------------------------------ build */
@@ -82,8 +84,9 @@ cng_status cng_build_workspace_size(int64_t n, int32_t d, const cng_build_params
 /* Build the graph (Algorithm 3 with exact candidates and fixed alpha).
  *   points  [n x d] float32;  2 <= n < 2^31 - 1, 1 <= d <= 4096.
  *   adj     [n x (R + extra)] uint32 output, CNG_NONE padded.  Columns 0..R-1
- *           hold the pruned out-neighbours in increasing (D, id); further
- *           columns only receive connectivity edges.
+ *           hold the pruned out-neighbours in increasing (D, id) (after the
+ *           backward-edge phase, if flagged); further columns only receive
+ *           connectivity edges.
  *   entry   [1] uint32 output: the point nearest the centroid (search entry).
  *   stats_host  optional (NULL allowed).
  * Synchronises `stream` (the connectivity phase is iterative) and returns
@@ -126,6 +129,21 @@ cng_status cng_knn(const float *rows, int64_t nr, const float *cols, int64_t nc,
 cng_status cng_prune(const float *points, int64_t n, int32_t d, const uint32_t *cand,
                      const float *candD, int32_t C, int32_t R, int32_t W, double alpha,
                      double tau, uint32_t *adj, void *stream);
+
+/* Stage: backward edges with lazy pruning (Algorithm 3, phase 3; Section 4.3)
+ * in place on adj [n x W] (rows end at their first CNG_NONE).  Every edge
+ * (u, v) adds the reverse edge (v, u).  The candidate set of p is its row
+ * together with the sources of its in-edges (a set), ordered by (D, id) with D
+ * in the fixed order, and cut to its Cb nearest (the paper bounds candidate
+ * sets by C).  A set of more than R points is pruned once as in cng_prune
+ * (same decision, at most R kept); a smaller one becomes p's row as it is.
+ * All sets are formed from the rows as they were before the call.
+ *   1 <= R <= W <= 256, 1 <= Cb <= 448.
+ * workspace >= cng_backward_workspace_size(n, W, Cb); enqueued on `stream`. */
+cng_status cng_backward_workspace_size(int64_t n, int32_t W, int32_t Cb, size_t *bytes_host);
+cng_status cng_backward(const float *points, int64_t n, int32_t d, uint32_t *adj, int32_t W,
+                        int32_t R, int32_t Cb, double alpha, double tau, void *workspace,
+                        size_t workspace_bytes, void *stream);
 
 /* Stage: connectivity (Algorithm 3, phase 4) in place on adj [n x W].
  * Rounds on a snapshot of the graph: let U be the points unreachable from

@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "cng.h")
 
 NONE = 0xFFFFFFFF
 BUILD_CONNECT = 1
+BUILD_BACKWARD = 2
 STATUS = {0: "CNG_OK", -1: "CNG_EINVAL", -2: "CNG_ENOMEM", -3: "CNG_EDEVICE",
           -4: "CNG_EUNSUPPORTED", -5: "CNG_ECAPACITY"}
 
@@ -43,7 +44,7 @@ class BuildStats(C.Structure):
                 ("ms_connect", C.c_double), ("ms_total", C.c_double),
                 ("connect_rounds", C.c_int64), ("connect_added", C.c_int64),
                 ("overflow_rows", C.c_int64), ("exact_integer", C.c_int32),
-                ("filter_dtype", C.c_int32)]
+                ("filter_dtype", C.c_int32), ("ms_backward", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -64,6 +65,9 @@ _SIGS = {
     "cng_knn": (C.c_int, [vp, i64, vp, i64, i32, i32, i32, i32, vp, vp, vp, sz, vp,
                           C.POINTER(i64)]),
     "cng_prune": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]),
+    "cng_backward_workspace_size": (C.c_int, [i64, i32, i32, C.POINTER(sz)]),
+    "cng_backward": (C.c_int, [vp, i64, i32, vp, i32, i32, i32, C.c_double, C.c_double, vp, sz,
+                               vp]),
     "cng_connect_workspace_size": (C.c_int, [i64, i32, i32, C.POINTER(sz)]),
     "cng_connect": (C.c_int, [vp, i64, i32, vp, i32, u32, i32, i32, vp, sz, vp, C.POINTER(i64),
                               C.POINTER(i64)]),
@@ -166,11 +170,14 @@ class Graph:
 
 
 def build(points: torch.Tensor, R: int, C_: int, alpha: float, tau: float = 0.0, extra: int = 1,
-          connect: bool = True, Lc: int = 0, band: int = 0, visited_log2: int = 0) -> Graph:
-    """cng_build: entry point, exact candidates, pruning, connectivity."""
+          connect: bool = True, Lc: int = 0, band: int = 0, visited_log2: int = 0,
+          backward: bool = False) -> Graph:
+    """cng_build: entry point, exact candidates, pruning, optional backward
+    edges, connectivity."""
     x = _f32(points)
     n, d = x.shape
-    p = BuildParams(R, extra, C_, alpha, tau, BUILD_CONNECT if connect else 0, Lc, band, visited_log2)
+    flags = (BUILD_CONNECT if connect else 0) | (BUILD_BACKWARD if backward else 0)
+    p = BuildParams(R, extra, C_, alpha, tau, flags, Lc, band, visited_log2)
     nb = sz(0)
     _check("cng_build_workspace_size", lib().cng_build_workspace_size(n, d, C.byref(p), C.byref(nb)))
     ws = _ws(nb.value, x.device)
@@ -221,6 +228,20 @@ def prune(points: torch.Tensor, cand: torch.Tensor, candD: torch.Tensor, R: int,
     _check("cng_prune", lib().cng_prune(_ptr(x), n, d, _ptr(cand), _ptr(candD), cand.shape[1], R, W,
                                         alpha, tau, _ptr(adj), _stream()))
     return adj
+
+
+def backward(points: torch.Tensor, adj: torch.Tensor, R: int, Cb: int, alpha: float,
+             tau: float = 0.0) -> None:
+    """cng_backward in place on adj (backward edges with lazy pruning)."""
+    x = _f32(points)
+    n, d = x.shape
+    adj = _ids(adj)
+    W = adj.shape[1]
+    nb = sz(0)
+    _check("cng_backward_workspace_size", lib().cng_backward_workspace_size(n, W, Cb, C.byref(nb)))
+    ws = _ws(nb.value, x.device)
+    _check("cng_backward", lib().cng_backward(_ptr(x), n, d, _ptr(adj), W, R, Cb, alpha, tau,
+                                              _ptr(ws), nb.value, _stream()))
 
 
 def connect(points: torch.Tensor, adj: torch.Tensor, entry: int, Lc: int, visited_log2: int = 0):

@@ -72,7 +72,7 @@ cng_status check_points(const void *p, int64_t n, int32_t d, int64_t nmin)
 struct BuildSizes {
     int Ceff, W, Lc;
     cng::KnnPlan knn;
-    size_t cand_ids, cand_D, entry, connect, total;
+    size_t cand_ids, cand_D, entry, connect, backward, total;
 };
 
 cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSizes *z)
@@ -102,9 +102,11 @@ cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSiz
     z->cand_D = align256((size_t)n * z->Ceff * 4);
     z->entry = align256(cng::entry_workspace_bytes(n, d));
     z->connect = align256(cng::connect_workspace_bytes(n, z->W, z->Lc));
+    z->backward = (p->flags & CNG_BUILD_BACKWARD) ? align256(cng::backward_workspace_bytes(n, z->W)) : 0;
     size_t scratch = z->entry;
     if (z->knn.bytes > scratch) scratch = z->knn.bytes;
     if (z->connect > scratch) scratch = z->connect;
+    if (z->backward > scratch) scratch = z->backward;
     z->total = z->cand_ids + z->cand_D + align256(scratch);
     return CNG_OK;
 }
@@ -172,6 +174,16 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
     if (e != hipSuccess) return hip_fail(e, "prune");
     const double t3 = now_ms();
 
+    // phase 3: the candidate arrays (n x Ceff) are free again and hold the
+    // candidate sets of the backward-edge phase
+    if (p->flags & CNG_BUILD_BACKWARD) {
+        e = cng::run_backward(points, n, d, adj, z.W, p->R, z.Ceff, p->alpha, p->tau, cand, candD,
+                              scratch, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "backward edges");
+    }
+    const double t3b = now_ms();
+
     int64_t rounds = 0, added = 0;
     if (p->flags & CNG_BUILD_CONNECT) {
         int cap = 0;
@@ -185,7 +197,8 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
     S->ms_entry = t1 - t0;
     S->ms_candidates = t2 - t1;
     S->ms_prune = t3 - t2;
-    S->ms_connect = t4 - t3;
+    S->ms_backward = t3b - t3;
+    S->ms_connect = t4 - t3b;
     S->ms_total = t4 - t0;
     S->connect_rounds = rounds;
     S->connect_added = added;
@@ -262,6 +275,39 @@ cng_status cng_prune(const float *points, int64_t n, int32_t d, const uint32_t *
     if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(CNG_EINVAL, "tau must be finite and >= 0");
     hipError_t e = cng::launch_prune(points, n, d, cand, candD, C, R, W, alpha, tau, adj, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "prune");
+    return ok();
+}
+
+cng_status cng_backward_workspace_size(int64_t n, int32_t W, int32_t Cb, size_t *bytes)
+{
+    if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
+    if (n < 1 || n > MAX_N || W < 1 || W > MAX_W) return fail(CNG_EINVAL, "n/W out of range");
+    if (Cb < 1 || Cb > 448) return fail(CNG_EUNSUPPORTED, "Cb=%d must be in [1, 448]", Cb);
+    *bytes = align256((size_t)n * Cb * 4) * 2 + cng::backward_workspace_bytes(n, W);
+    return ok();
+}
+
+cng_status cng_backward(const float *points, int64_t n, int32_t d, uint32_t *adj, int32_t W,
+                        int32_t R, int32_t Cb, double alpha, double tau, void *workspace,
+                        size_t ws_bytes, void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    size_t need = 0;
+    s = cng_backward_workspace_size(n, W, Cb, &need);
+    if (s != CNG_OK) return s;
+    if (!adj) return fail(CNG_EINVAL, "adj is NULL");
+    if (R < 1 || R > W) return fail(CNG_EINVAL, "need 1 <= R <= W");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(CNG_EINVAL, "alpha must be finite and > 0");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(CNG_EINVAL, "tau must be finite and >= 0");
+    if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    unsigned char *w = (unsigned char *)workspace;
+    uint32_t *cand = (uint32_t *)w;
+    float *candD = (float *)(w + align256((size_t)n * Cb * 4));
+    void *rest = w + align256((size_t)n * Cb * 4) * 2;
+    hipError_t e = cng::run_backward(points, n, d, adj, W, R, Cb, alpha, tau, cand, candD, rest,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "backward edges");
     return ok();
 }
 

@@ -28,6 +28,7 @@ struct PruneArgs {
     int C, R, W;
     double alpha, tau;
     uint32_t *adj;
+    int copy_upto;  // > 0: a list of at most this many candidates is copied, not pruned
 };
 
 template <int G, int RND, bool VEC>
@@ -55,6 +56,22 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
     uint32_t *S = reinterpret_cast<uint32_t *>(smem) + (size_t)wave * a.R;
     const int d = a.d;
 
+    if (a.copy_upto > 0 &&
+        (a.C <= a.copy_upto || a.cand[(size_t)p * a.C + a.copy_upto] == NONE)) {
+        // short list: it becomes the row as it is (lazy pruning, Section 4.3)
+        uint32_t *out = a.adj + (size_t)p * a.W;
+        bool alive = true;
+        for (int s0 = 0; s0 < a.W; s0 += 64) {
+            const int s = s0 + lane;
+            uint32_t u = s < a.C && s < a.copy_upto ? a.cand[(size_t)p * a.C + s] : NONE;
+            const bool ok = alive && u != NONE && (int64_t)u < a.n;
+            const uint64_t bad = ballot(!ok);
+            const int first_bad = bad ? __builtin_ctzll(bad) : 64;
+            if (s < a.W) out[s] = ok && lane < first_bad ? u : NONE;
+            if (bad) alive = false;
+        }
+        return;
+    }
     const float al = (float)a.alpha, ta = (float)a.tau;
     const float cterm = (al + 1.0f) * ta;
     const float *xp = a.points + (size_t)p * d;
@@ -151,10 +168,10 @@ PruneFn pick_prune(int d)
 
 hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *cand,
                         const float *candD, int C, int R, int W, double alpha, double tau,
-                        uint32_t *adj, hipStream_t stream)
+                        uint32_t *adj, hipStream_t stream, int copy_upto)
 {
     if (n == 0) return hipSuccess;
-    PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj};
+    PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj, copy_upto};
     const bool vec = (d % 4 == 0) && ((uintptr_t)points % 16 == 0);
     PruneFn fn = vec ? pick_prune<true>(d) : pick_prune<false>(d);
     const int wpb = 4;
