@@ -56,6 +56,9 @@ def lib():
         L.orc_knn.argtypes = [f32p, i64, f32p, i64, C.c_int, C.c_int, C.c_int, C.c_int, u32p, f64p]
         L.orc_prune.argtypes = [f32p, i64, C.c_int, u32p, f64p, C.c_int, C.c_int, C.c_int,
                                 C.c_double, C.c_double, C.c_int, u32p]
+        L.orc_prune_adaptive.argtypes = [f32p, i64, C.c_int, u32p, f64p, C.c_int, C.c_int,
+                                         C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                         C.c_int, u32p]
         L.orc_medoid.restype = C.c_uint32
         L.orc_medoid.argtypes = [f32p, i64, C.c_int]
         L.orc_search.argtypes = [f32p, i64, C.c_int, u32p, C.c_int, f32p, i64, C.c_int, C.c_int,
@@ -66,10 +69,10 @@ def lib():
         L.orc_connect.argtypes = [f32p, i64, C.c_int, u32p, C.c_int, C.c_uint32, C.c_int, C.c_int,
                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.orc_build.argtypes = [f32p, i64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
-                                C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, u32p,
-                                C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
+                                C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                C.c_int, u32p, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
         L.orc_backward.argtypes = [f32p, i64, C.c_int, u32p, C.c_int, C.c_int, C.c_int,
-                                   C.c_double, C.c_double, C.c_int]
+                                   C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
         L.orc_round_bf16.restype = C.c_float
         L.orc_round_bf16.argtypes = [C.c_float]
         L.orc_round_e4m3.restype = C.c_float
@@ -124,16 +127,19 @@ def knn(rows, cols, C: int, exclude_self: bool = False, mode: int = FP32):
 
 
 def prune(points, cand, candD, R: int, alpha: float, tau: float = 0.0, mode: int = FP32,
-          width: int | None = None):
-    """Alg. 2 on every candidate row, at most R kept -> adjacency (n x width, NONE padded)."""
+          width: int | None = None, alpha_max: float | None = None, alpha_step: float = 0.0):
+    """Alg. 2 on every candidate row, at most R kept -> adjacency (n x width,
+    NONE padded).  alpha_step > 0: Alg. 4 (adaptive alpha from ``alpha`` up to
+    ``alpha_max``)."""
     points = _f32(points)
     n, d = points.shape
     W = R if width is None else width
     cand = np.ascontiguousarray(cand, np.uint32)
     candD = np.ascontiguousarray(candD, np.float64)
     adj = np.empty((n, W), np.uint32)
-    _check(lib().orc_prune(points, n, d, cand, candD, cand.shape[1], R, W, alpha, tau, mode, adj),
-           "prune")
+    amax = alpha if alpha_max is None else alpha_max
+    _check(lib().orc_prune_adaptive(points, n, d, cand, candD, cand.shape[1], R, W, alpha, amax,
+                                    alpha_step, tau, mode, adj), "prune")
     return adj
 
 
@@ -184,26 +190,32 @@ def connect(points, adj, entry: int, Lc: int, mode: int = FP32):
     return adj, added.value, rounds.value
 
 
-def backward(points, adj, R: int, Cb: int, alpha: float, tau: float = 0.0, mode: int = FP32):
+def backward(points, adj, R: int, Cb: int, alpha: float, tau: float = 0.0, mode: int = FP32,
+             alpha_max: float | None = None, alpha_step: float = 0.0):
     """Alg. 3 phase 3 (backward edges, lazy pruning) on a copy of ``adj``."""
     points = _f32(points)
     n, d = points.shape
     adj = np.array(adj, np.uint32, copy=True, order="C")
-    _check(lib().orc_backward(points, n, d, adj, R, adj.shape[1], Cb, alpha, tau, mode),
-           "backward")
+    amax = alpha if alpha_max is None else alpha_max
+    _check(lib().orc_backward(points, n, d, adj, R, adj.shape[1], Cb, alpha, amax, alpha_step,
+                              tau, mode), "backward")
     return adj
 
 
 def build(points, R: int, C_: int, alpha: float, tau: float = 0.0, mode: int = FP32,
-          connect: bool = True, Lc: int = 0, extra: int = 1, backward: bool = False):
-    """Whole fixed-alpha build -> (adj (n x (R + extra)), entry, n_added)."""
+          connect: bool = True, Lc: int = 0, extra: int = 1, backward: bool = False,
+          alpha_max: float | None = None, alpha_step: float = 0.0):
+    """Whole build -> (adj (n x (R + extra)), entry, n_added).  alpha_step > 0:
+    adaptive alpha (Alg. 4) from ``alpha`` to ``alpha_max``."""
     points = _f32(points)
     n, d = points.shape
     adj = np.empty((n, R + extra), np.uint32)
     entry = C.c_uint32(0)
     added = C.c_int64(0)
-    _check(lib().orc_build(points, n, d, R, extra, C_, alpha, tau, mode, int(connect),
-                           int(backward), Lc, adj, C.byref(entry), C.byref(added)), "build")
+    amax = alpha if alpha_max is None else alpha_max
+    _check(lib().orc_build(points, n, d, R, extra, C_, alpha, amax, alpha_step, tau, mode,
+                           int(connect), int(backward), Lc, adj, C.byref(entry), C.byref(added)),
+           "build")
     return adj, int(entry.value), added.value
 
 

@@ -226,17 +226,40 @@ static int prune_sorted(const float *pts, int d, uint32_t p, const orc_key *V, i
     return ns;
 }
 
+/* Alg. 4 adaptive-pruning(p, V, M, alpha0, alpha_max, dalpha) on a sorted V:
+ * alpha_i = alpha0 + i * dalpha for i = 0, 1, ... while alpha_i <= alpha_max
+ * (up to 1e-9 of slack, so that alpha_max itself is reached despite rounding);
+ * the first alpha_i whose shortcut set holds at least M/2 points ends the
+ * loop (else the last one stands), and the M closest points of that set are
+ * returned (the pruning stops once M are kept).  dalpha <= 0: one pass with
+ * alpha0 (fixed alpha). */
+static int prune_select(const float *pts, int d, uint32_t p, const orc_key *V, int nv, int M,
+                        double alpha0, double alpha_max, double dalpha, double tau, int mode,
+                        uint32_t *S)
+{
+    if (!(dalpha > 0.0)) return prune_sorted(pts, d, p, V, nv, M, alpha0, tau, mode, S);
+    const int h = (int)floor((alpha_max - alpha0) / dalpha + 1e-9);
+    int ns = 0;
+    for (int i = 0; i <= h; ++i) {
+        ns = prune_sorted(pts, d, p, V, nv, M, alpha0 + i * dalpha, tau, mode, S);
+        if (2 * ns >= M) break;
+    }
+    return ns;
+}
+
 /* Alg. 2 pruning(p, V, alpha) on the candidate list of every point, keeping at
  * most R out-neighbours, written into rows of width W >= R (padded with
  * ORC_NONE; slots beyond R are spare slots for connectivity edges).  Stopping once R are kept equals returning the R
  * closest points of the full shortcut set (the decision for u only involves
  * earlier kept points).  Candidate lists are re-sorted by (D, id) first
  * (Alg. 2 line 1); entries equal to ORC_NONE end a list. */
-int orc_prune(const float *pts, int64_t n, int d, const uint32_t *cand, const double *candD,
-              int C, int R, int W, double alpha, double tau, int mode, uint32_t *adj)
+int orc_prune_adaptive(const float *pts, int64_t n, int d, const uint32_t *cand,
+                       const double *candD, int C, int R, int W, double alpha, double alpha_max,
+                       double dalpha, double tau, int mode, uint32_t *adj)
 {
     if (n < 1 || d < 1 || C < 1 || R < 1 || W < R || !(alpha > 0.0) || !(tau >= 0.0))
         return ORC_EINVAL;
+    if (dalpha > 0.0 && !(alpha_max >= alpha)) return ORC_EINVAL;
     int fail = 0;
 #pragma omp parallel
     {
@@ -258,7 +281,8 @@ int orc_prune(const float *pts, int64_t n, int d, const uint32_t *cand, const do
                 ++nv;
             }
             qsort(V, (size_t)nv, sizeof(orc_key), cmp_key);
-            int ns = prune_sorted(pts, d, (uint32_t)p, V, nv, R, alpha, tau, mode, S);
+            int ns = prune_select(pts, d, (uint32_t)p, V, nv, R, alpha, alpha_max, dalpha, tau,
+                                  mode, S);
             for (int s = 0; s < W; ++s) adj[(size_t)p * W + s] = s < ns ? S[s] : ORC_NONE;
         }
         free(V);
@@ -267,21 +291,29 @@ int orc_prune(const float *pts, int64_t n, int d, const uint32_t *cand, const do
     return fail ? ORC_ENOMEM : ORC_OK;
 }
 
+int orc_prune(const float *pts, int64_t n, int d, const uint32_t *cand, const double *candD,
+              int C, int R, int W, double alpha, double tau, int mode, uint32_t *adj)
+{
+    return orc_prune_adaptive(pts, n, d, cand, candD, C, R, W, alpha, alpha, 0.0, tau, mode, adj);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Alg. 3 phase 3: backward edges with lazy pruning (Section 4.3).  For every  */
 /* edge (u, v) of the pruned graph the reverse edge (v, u) is added.  Each      */
 /* point's candidate set V is its out-neighbours together with the sources of  */
 /* the edges into it (a set), ordered by (D, id).  The paper bounds candidate  */
 /* sets by C; here V is cut to its Cb nearest.  A point with |V| > R is pruned  */
-/* once over V (Alg. 2, cap R); otherwise V itself becomes its row (in (D, id)  */
+/* once over V (Alg. 2 with cap R, or Alg. 4 when dalpha > 0); otherwise V     */
+/* itself becomes its row (in (D, id)                                           */
 /* order; the order of a row does not change Alg. 1).  Every decision reads    */
 /* the graph as it was before this phase.  Rows have width W >= R.             */
 /* ------------------------------------------------------------------------- */
 int orc_backward(const float *pts, int64_t n, int d, uint32_t *adj, int R, int W, int Cb,
-                 double alpha, double tau, int mode)
+                 double alpha, double alpha_max, double dalpha, double tau, int mode)
 {
     if (n < 1 || d < 1 || R < 1 || W < R || Cb < 1 || !(alpha > 0.0) || !(tau >= 0.0))
         return ORC_EINVAL;
+    if (dalpha > 0.0 && !(alpha_max >= alpha)) return ORC_EINVAL;
     int64_t *off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     uint32_t *out = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * W);
@@ -356,7 +388,8 @@ int orc_backward(const float *pts, int64_t n, int d, uint32_t *adj, int R, int W
                 for (int64_t j = 0; j < m; ++j) S[j] = V[j].id;
                 ns = (int)m;
             } else {
-                ns = prune_sorted(pts, d, (uint32_t)p, V, (int)m, R, alpha, tau, mode, S);
+                ns = prune_select(pts, d, (uint32_t)p, V, (int)m, R, alpha, alpha_max, dalpha,
+                                  tau, mode, S);
             }
             for (int s = 0; s < W; ++s) row[s] = s < ns ? S[s] : ORC_NONE;
         }
@@ -814,14 +847,15 @@ done:
 }
 
 /* ------------------------------------------------------------------------- */
-/* Whole build with a fixed alpha: entry point, exact candidates, pruning of    */
-/* each candidate list (Alg. 2 with cap R), optionally backward edges with     */
-/* lazy pruning (phase 3), then connectivity.  Rows have width R + extra; the  */
-/* extra slots only ever hold connectivity edges.                               */
+/* Whole build: entry point, exact candidates, pruning of each candidate list  */
+/* (Alg. 2 with cap R and fixed alpha, or Alg. 4's adaptive alpha when         */
+/* dalpha > 0), optionally backward edges with lazy pruning (phase 3, the same */
+/* pruning), then connectivity.  Rows have width R + extra; the extra slots    */
+/* only ever hold connectivity edges.                                           */
 /* ------------------------------------------------------------------------- */
-int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, double alpha, double tau,
-              int mode, int connect, int backward, int Lc, uint32_t *adj, uint32_t *entry,
-              int64_t *n_added)
+int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, double alpha,
+              double alpha_max, double dalpha, double tau, int mode, int connect, int backward,
+              int Lc, uint32_t *adj, uint32_t *entry, int64_t *n_added)
 {
     if (n < 2 || d < 1 || R < 1 || extra < 0 || C < 1) return ORC_EINVAL;
     int W = R + extra;
@@ -833,9 +867,10 @@ int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, doubl
     *entry = orc_medoid(pts, n, d);
     rc = orc_knn(pts, n, pts, n, d, Ce, 1, mode, cand, cD);
     if (rc) goto out;
-    rc = orc_prune(pts, n, d, cand, cD, Ce, R, W, alpha, tau, mode, adj);
+    rc = orc_prune_adaptive(pts, n, d, cand, cD, Ce, R, W, alpha, alpha_max, dalpha, tau, mode,
+                            adj);
     if (rc) goto out;
-    if (backward) rc = orc_backward(pts, n, d, adj, R, W, Ce, alpha, tau, mode);
+    if (backward) rc = orc_backward(pts, n, d, adj, R, W, Ce, alpha, alpha_max, dalpha, tau, mode);
     if (rc) goto out;
     if (n_added) *n_added = 0;
     if (connect) rc = orc_connect(pts, n, d, adj, W, *entry, Lc > 0 ? Lc : Ce, mode, n_added, NULL);
