@@ -32,8 +32,8 @@ def test_hand_worked():
         cD[0] = [oracle.dist_f64(x[0], x[v]) for v in case["cand0"]]
         for run in case["runs"]:
             for mode in (oracle.FP32, oracle.FP64):
-                a = oracle.prune(x, cand, cD, run["M"], 0.9, mode=mode, alpha_max=run["alpha_max"],
-                                 alpha_step=0.05)
+                a = oracle.prune(x, cand, cD, run["M"], run.get("alpha0", 0.9), mode=mode,
+                                 alpha_max=run["alpha_max"], alpha_step=run.get("alpha_step", 0.05))
                 assert _row(a) == run["row0"], (run, mode)
 
 
