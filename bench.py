@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16/fp8, learned-entry and serving legs")
     ap.add_argument("--backward", action="store_true",
                     help="build with backward edges and lazy pruning (Algorithm 3, phase 3)")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive-alpha (Algorithm 4) + backward-edge leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-entry leg")
     ap.add_argument("--learn-n", type=int, default=1_000_000, help="base size of the vMF learned-entry leg")
@@ -137,23 +139,22 @@ def main():
     print(f"# build {g.stats}", file=sys.stderr, flush=True)
 
     # ---- beam sweep: the smallest L with tie-aware recall@10 >= 0.95
-    sweep = []
-    Ls = [a.L] if a.L else cfg["L"]
-    chosen = None
-    for L in Ls:
+    def eval_fp32(L):
         ids, dists, hops, ndc = search(g, L, vlog2=14, stats=True)
         torch.cuda.synchronize()
         s, tw = recall(cng.u32(ids), gt_ids, gt_dk, dists.cpu().numpy())
         row = dict(L=L, recall_strict=round(s, 4), recall_tie=round(tw, 4),
                    hops=float(hops.float().mean()), ndc=float(ndc.float().mean()))
-        sweep.append(row)
         print(f"# sweep {row}", file=sys.stderr, flush=True)
-        if chosen is None and tw >= 0.95:
-            chosen = row
-            if not a.L:
-                break
-    if chosen is None:
-        chosen = sweep[-1]
+        return row, None
+
+    if a.L:
+        chosen, _ = eval_fp32(a.L)
+        sweep = [chosen]
+    else:
+        chosen, _, sweep = sweep_L(eval_fp32, cfg["L"])
+        if chosen is None:
+            chosen = sweep[-1]
     L = chosen["L"]
     # algorithmic work of one query batch (no repeated evaluations)
     _, _, hops_t, ndc_t = search(g, L, vlog2=14, stats=True)
@@ -271,12 +272,18 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, cng.u32(g.adj), g.entry, k, L, a.cpu_seconds)
     if not a.no_forms and not a.search_only:
-        fp32_by_L = {r["L"]: r for r in sweep}
+        known = {r["L"]: r["recall_tie"] for r in sweep}
+
+        def fp32_by_L(L):
+            return known[L] if L in known else eval_fp32(L)[0]["recall_tie"]
         forms = {}
         for name, dt in (("bf16", cng.BF16), ("fp8", cng.FP8)):
             forms[name] = quant_form(cng, torch, x, q, xd, qd, g, dt, gt_ids, gt_dk, k, cfg["L"],
                                      fp32_by_L, a.search_reps)
             print(f"# form {name} {forms[name]}", file=sys.stderr, flush=True)
+        if not a.no_adaptive:
+            forms["adaptive_alpha"] = adaptive_form(cng, torch, xd, qd, gt_ids, gt_dk, cfg, a)
+            print(f"# adaptive {forms['adaptive_alpha']}", file=sys.stderr, flush=True)
         if not a.no_serving:
             forms["serving"] = serving_form(cng, torch, x, q, xd, g, gt_ids, a)
             print(f"# serving {forms['serving']}", file=sys.stderr, flush=True)
@@ -287,6 +294,29 @@ def main():
             forms["learned_entry_vmf"] = learned_form(cng, torch, a, 4, None)
         out["forms"] = forms
     print(json.dumps(out))
+
+
+def sweep_L(eval_fn, Ls, target=0.95):
+    """Smallest beam width reaching tie-aware recall@10 >= target: the coarse
+    grid ``Ls`` first, then steps of 8 between the last width below the target
+    and the first above it.  eval_fn(L) -> (row dict with 'recall_tie', payload).
+    Returns (row, payload, rows) with row None if the target is not reached."""
+    rows, prev = [], None
+    for L in Ls:
+        row, pay = eval_fn(L)
+        rows.append(row)
+        if row["recall_tie"] >= target:
+            best = (row, pay)
+            if prev is not None:
+                for L2 in range(prev + 8, L, 8):
+                    r2, p2 = eval_fn(L2)
+                    rows.append(r2)
+                    if r2["recall_tie"] >= target:
+                        best = (r2, p2)
+                        break
+            return best[0], best[1], sorted(rows, key=lambda r: r["L"])
+        prev = L
+    return None, None, rows
 
 
 def timed(torch, fn, reps):
@@ -311,21 +341,19 @@ def quant_form(cng, torch, x, q, xd, qd, g, dtype, gt_ids, gt_dk, k, Ls, fp32_by
     n, d = x.shape
     nq = q.shape[0]
     W = g.adj.shape[1]
-    sweep, chosen = [], None
-    for L in Ls:
+    def eval_q(L):
         ids, dists, hops, ndc = cng.search_quantized(xd, st, g.adj, qd, k, L, g.entry, visited_log2=14,
                                                      stats=True)
         torch.cuda.synchronize()
         s_, tw = recall(cng.u32(ids), gt_ids, gt_dk, dists.cpu().numpy())
         row = dict(L=L, recall_tie=round(tw, 4), recall_strict=round(s_, 4),
                    hops=float(hops.float().mean()), ndc=float(ndc.float().mean()))
-        sweep.append(row)
-        if tw >= 0.95:
-            chosen = (row, cng.u32(ids), dists.cpu().numpy())
-            break
-    if chosen is None:
+        return row, (cng.u32(ids), dists.cpu().numpy())
+
+    row, pay, sweep = sweep_L(eval_q, Ls)
+    if row is None:
         return {"sweep": sweep, "note": "recall 0.95 not reached"}
-    row, ids, dists = chosen
+    ids, dists = pay
     L = row["L"]
     ms = timed(torch, lambda: cng.search_quantized(xd, st, g.adj, qd, k, L, g.entry), reps)
     b = 2 if dtype == cng.BF16 else 1
@@ -338,16 +366,50 @@ def quant_form(cng, torch, x, q, xd, qd, g, dtype, gt_ids, gt_dk, k, Ls, fp32_by
     ref = np.sqrt(((X64[ids[:m]] - q[:m, None, :].astype(np.float64)) ** 2).sum(-1))
     ok = ref > 0
     rel = np.abs(dists[:m].astype(np.float64) - ref)[ok] / ref[ok]
-    base = fp32_by_L.get(L)
+    base = fp32_by_L(L)
     return {"L": L, "qps": round(nq / (ms / 1e3), 1), "search_ms": round(ms, 4),
             "recall@10": row["recall_tie"], "recall@10_strict": row["recall_strict"],
-            "recall_loss_vs_fp32_same_L": None if base is None else
-            round(base["recall_tie"] - row["recall_tie"], 4),
+            "recall_loss_vs_fp32_same_L": round(base - row["recall_tie"], 4),
             "dist_rel_err_vs_fp64": {"max": float(rel.max()), "mean": float(rel.mean())},
             "hops_mean": row["hops"], "ndc_mean": row["ndc"], "quantize_s": round(qsec, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
             "sweep": sweep}
+
+
+def adaptive_form(cng, torch, xd, qd, gt_ids, gt_dk, cfg, a):
+    """The paper's alpha-CNG: adaptive alpha (Algorithm 4; alpha0 = 0.9, step
+    0.05, alpha_max = 1.6) with backward edges and lazy pruning (Algorithm 3,
+    phase 3), same R and C; float32 search QPS at recall@10 >= 0.95."""
+    k = cfg["k"]
+    nq = qd.shape[0]
+    bts = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = cng.build(xd, cfg["R"], cfg["C"], 0.9, cfg["tau"], alpha_max=1.6, alpha_step=0.05,
+                      backward=True)
+        torch.cuda.synchronize()
+        bts.append(time.perf_counter() - t0)
+    out = {"alpha0": 0.9, "alpha_step": 0.05, "alpha_max": 1.6, "backward_edges": True,
+           "build_secs": round(min(bts), 4),
+           "build_stages_ms": {kk: round(g.stats[kk], 2) for kk in
+                               ("ms_candidates", "ms_prune", "ms_backward", "ms_connect")},
+           "mean_degree": round(float((g.adj != -1).sum(1).float().mean()), 2), "sweep": []}
+    def eval_a(L):
+        ids, dd, hops, ndc = cng.search(xd, g.adj, qd, k, L, g.entry, visited_log2=14, stats=True)
+        torch.cuda.synchronize()
+        s_, tw = recall(cng.u32(ids), gt_ids, gt_dk, dd.cpu().numpy())
+        return dict(L=L, recall_tie=round(tw, 4), recall_strict=round(s_, 4),
+                    hops=float(hops.float().mean()), ndc=float(ndc.float().mean())), None
+
+    row, _, out["sweep"] = sweep_L(eval_a, cfg["L"])
+    if row is not None:
+        L = row["L"]
+        ms = timed(torch, lambda: cng.search(xd, g.adj, qd, k, L, g.entry), a.search_reps)
+        out.update(L=L, qps=round(nq / (ms / 1e3), 1), search_ms=round(ms, 4),
+                   recall_at_L=row["recall_tie"])
+    return out
 
 
 def serving_form(cng, torch, x, q, xd, g, gt_ids, a):
@@ -496,16 +558,17 @@ def learned_form(cng, torch, a, cfg_id, prepared):
            "final_loss": model.history[-1][1], "val_label_accuracy": round(acc, 4),
            "theta": model.theta, "variants": {}}
     for name, (efn, store) in variants.items():
-        got = None
-        curve = []
-        for L in cfg["L"]:
+        def eval_v(L, efn=efn, store=store):
             tw, go = run(efn, store, L)
-            curve.append((L, round(tw, 4)))
-            if tw >= 0.95:
-                ms = timed(torch, go, a.search_reps)
-                got = {"L": L, "recall@10": round(tw, 4), "qps": round(nq / (ms / 1e3), 1),
-                       "ms": round(ms, 4)}
-                break
+            return {"L": L, "recall_tie": round(tw, 4)}, go
+
+        row, go, rows = sweep_L(eval_v, cfg["L"])
+        got = None
+        if row is not None:
+            ms = timed(torch, go, a.search_reps)
+            got = {"L": row["L"], "recall@10": row["recall_tie"], "qps": round(nq / (ms / 1e3), 1),
+                   "ms": round(ms, 4)}
+        curve = [(r["L"], r["recall_tie"]) for r in rows]
         out["variants"][name] = dict(got or {"note": "recall 0.95 not reached"}, curve=curve)
         print(f"# learned {name} {out['variants'][name]}", file=sys.stderr, flush=True)
     return out

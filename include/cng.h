@@ -63,6 +63,8 @@ typedef struct {
     int32_t Lc;          /* beam width of the connectivity searches (0 = C) */
     int32_t band;        /* per-row capacity of the candidate filter (0 = automatic) */
     int32_t visited_log2;/* log2 of the search visited-table slots (0 = automatic) */
+    double alpha_max;    /* adaptive alpha (Algorithm 4): largest alpha tried, >= alpha */
+    double alpha_step;   /* adaptive alpha step; 0 = fixed alpha (Algorithm 2 alone) */
 } cng_build_params;
 
 typedef struct {
@@ -130,19 +132,32 @@ cng_status cng_prune(const float *points, int64_t n, int32_t d, const uint32_t *
                      const float *candD, int32_t C, int32_t R, int32_t W, double alpha,
                      double tau, uint32_t *adj, void *stream);
 
+/* Stage: adaptive local pruning (Algorithm 4, Section 4.2) with the rule of
+ * cng_prune.  For every point the pruning runs with alpha_i = alpha0 + i *
+ * alpha_step, i = 0, 1, ... while alpha_i <= alpha_max (with 1e-9 of slack in
+ * units of the step); the first pass whose kept set holds at least R/2 points
+ * stands (else the pass at alpha_max), and it keeps at most R points (its R
+ * closest).  alpha_step > 0, alpha_max >= alpha0; at most 1024 passes. */
+cng_status cng_prune_adaptive(const float *points, int64_t n, int32_t d, const uint32_t *cand,
+                              const float *candD, int32_t C, int32_t R, int32_t W, double alpha0,
+                              double alpha_max, double alpha_step, double tau, uint32_t *adj,
+                              void *stream);
+
 /* Stage: backward edges with lazy pruning (Algorithm 3, phase 3; Section 4.3)
  * in place on adj [n x W] (rows end at their first CNG_NONE).  Every edge
  * (u, v) adds the reverse edge (v, u).  The candidate set of p is its row
  * together with the sources of its in-edges (a set), ordered by (D, id) with D
  * in the fixed order, and cut to its Cb nearest (the paper bounds candidate
  * sets by C).  A set of more than R points is pruned once as in cng_prune
- * (same decision, at most R kept); a smaller one becomes p's row as it is.
- * All sets are formed from the rows as they were before the call.
+ * (alpha_step = 0) or cng_prune_adaptive (alpha_step > 0, alpha from alpha to
+ * alpha_max), at most R kept; a smaller one becomes p's row as it is.  All
+ * sets are formed from the rows as they were before the call.
  *   1 <= R <= W <= 256, 1 <= Cb <= 448.
  * workspace >= cng_backward_workspace_size(n, W, Cb); enqueued on `stream`. */
 cng_status cng_backward_workspace_size(int64_t n, int32_t W, int32_t Cb, size_t *bytes_host);
 cng_status cng_backward(const float *points, int64_t n, int32_t d, uint32_t *adj, int32_t W,
-                        int32_t R, int32_t Cb, double alpha, double tau, void *workspace,
+                        int32_t R, int32_t Cb, double alpha, double alpha_max,
+                        double alpha_step, double tau, void *workspace,
                         size_t workspace_bytes, void *stream);
 
 /* Stage: connectivity (Algorithm 3, phase 4) in place on adj [n x W].

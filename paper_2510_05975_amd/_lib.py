@@ -36,7 +36,7 @@ class CngError(RuntimeError):
 class BuildParams(C.Structure):
     _fields_ = [("R", C.c_int32), ("extra", C.c_int32), ("C", C.c_int32), ("alpha", C.c_double),
                 ("tau", C.c_double), ("flags", C.c_uint32), ("Lc", C.c_int32), ("band", C.c_int32),
-                ("visited_log2", C.c_int32)]
+                ("visited_log2", C.c_int32), ("alpha_max", C.c_double), ("alpha_step", C.c_double)]
 
 
 class BuildStats(C.Structure):
@@ -65,8 +65,11 @@ _SIGS = {
     "cng_knn": (C.c_int, [vp, i64, vp, i64, i32, i32, i32, i32, vp, vp, vp, sz, vp,
                           C.POINTER(i64)]),
     "cng_prune": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]),
+    "cng_prune_adaptive": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, vp, vp]),
     "cng_backward_workspace_size": (C.c_int, [i64, i32, i32, C.POINTER(sz)]),
-    "cng_backward": (C.c_int, [vp, i64, i32, vp, i32, i32, i32, C.c_double, C.c_double, vp, sz,
+    "cng_backward": (C.c_int, [vp, i64, i32, vp, i32, i32, i32, C.c_double, C.c_double,
+                               C.c_double, C.c_double, vp, sz,
                                vp]),
     "cng_connect_workspace_size": (C.c_int, [i64, i32, i32, C.POINTER(sz)]),
     "cng_connect": (C.c_int, [vp, i64, i32, vp, i32, u32, i32, i32, vp, sz, vp, C.POINTER(i64),
@@ -171,13 +174,15 @@ class Graph:
 
 def build(points: torch.Tensor, R: int, C_: int, alpha: float, tau: float = 0.0, extra: int = 1,
           connect: bool = True, Lc: int = 0, band: int = 0, visited_log2: int = 0,
-          backward: bool = False) -> Graph:
-    """cng_build: entry point, exact candidates, pruning, optional backward
-    edges, connectivity."""
+          backward: bool = False, alpha_max: float | None = None,
+          alpha_step: float = 0.0) -> Graph:
+    """cng_build: entry point, exact candidates, pruning (adaptive alpha when
+    alpha_step > 0), optional backward edges, connectivity."""
     x = _f32(points)
     n, d = x.shape
     flags = (BUILD_CONNECT if connect else 0) | (BUILD_BACKWARD if backward else 0)
-    p = BuildParams(R, extra, C_, alpha, tau, flags, Lc, band, visited_log2)
+    amax = alpha if alpha_max is None else alpha_max
+    p = BuildParams(R, extra, C_, alpha, tau, flags, Lc, band, visited_log2, amax, alpha_step)
     nb = sz(0)
     _check("cng_build_workspace_size", lib().cng_build_workspace_size(n, d, C.byref(p), C.byref(nb)))
     ws = _ws(nb.value, x.device)
@@ -219,19 +224,27 @@ def knn(rows: torch.Tensor, cols: torch.Tensor, C_: int, exclude_self: bool = Fa
 
 
 def prune(points: torch.Tensor, cand: torch.Tensor, candD: torch.Tensor, R: int, alpha: float,
-          tau: float = 0.0, width: int | None = None) -> torch.Tensor:
+          tau: float = 0.0, width: int | None = None, alpha_max: float | None = None,
+          alpha_step: float = 0.0) -> torch.Tensor:
+    """cng_prune (fixed alpha) or, with alpha_step > 0, cng_prune_adaptive."""
     x = _f32(points)
     n, d = x.shape
     cand, candD = _ids(cand), candD.contiguous()
     W = R if width is None else width
     adj = torch.empty((n, W), dtype=torch.int32, device=x.device)
-    _check("cng_prune", lib().cng_prune(_ptr(x), n, d, _ptr(cand), _ptr(candD), cand.shape[1], R, W,
-                                        alpha, tau, _ptr(adj), _stream()))
+    if alpha_step > 0:
+        amax = alpha if alpha_max is None else alpha_max
+        _check("cng_prune_adaptive", lib().cng_prune_adaptive(
+            _ptr(x), n, d, _ptr(cand), _ptr(candD), cand.shape[1], R, W, alpha, amax, alpha_step,
+            tau, _ptr(adj), _stream()))
+    else:
+        _check("cng_prune", lib().cng_prune(_ptr(x), n, d, _ptr(cand), _ptr(candD), cand.shape[1],
+                                            R, W, alpha, tau, _ptr(adj), _stream()))
     return adj
 
 
 def backward(points: torch.Tensor, adj: torch.Tensor, R: int, Cb: int, alpha: float,
-             tau: float = 0.0) -> None:
+             tau: float = 0.0, alpha_max: float | None = None, alpha_step: float = 0.0) -> None:
     """cng_backward in place on adj (backward edges with lazy pruning)."""
     x = _f32(points)
     n, d = x.shape
@@ -240,8 +253,9 @@ def backward(points: torch.Tensor, adj: torch.Tensor, R: int, Cb: int, alpha: fl
     nb = sz(0)
     _check("cng_backward_workspace_size", lib().cng_backward_workspace_size(n, W, Cb, C.byref(nb)))
     ws = _ws(nb.value, x.device)
-    _check("cng_backward", lib().cng_backward(_ptr(x), n, d, _ptr(adj), W, R, Cb, alpha, tau,
-                                              _ptr(ws), nb.value, _stream()))
+    amax = alpha if alpha_max is None else alpha_max
+    _check("cng_backward", lib().cng_backward(_ptr(x), n, d, _ptr(adj), W, R, Cb, alpha, amax,
+                                              alpha_step, tau, _ptr(ws), nb.value, _stream()))
 
 
 def connect(points: torch.Tensor, adj: torch.Tensor, entry: int, Lc: int, visited_log2: int = 0):

@@ -69,6 +69,15 @@ cng_status check_points(const void *p, int64_t n, int32_t d, int64_t nmin)
     return CNG_OK;
 }
 
+cng_status check_adaptive(double alpha0, double alpha_max, double alpha_step)
+{
+    if (alpha_step == 0.0) return CNG_OK;
+    if (!(alpha_step > 0.0) || !std::isfinite(alpha_step)) return fail(CNG_EINVAL, "alpha_step must be finite and >= 0");
+    if (!(alpha_max >= alpha0) || !std::isfinite(alpha_max)) return fail(CNG_EINVAL, "alpha_max must be finite and >= alpha");
+    if ((alpha_max - alpha0) / alpha_step > 1023.0) return fail(CNG_EUNSUPPORTED, "more than 1024 alpha passes");
+    return CNG_OK;
+}
+
 struct BuildSizes {
     int Ceff, W, Lc;
     cng::KnnPlan knn;
@@ -86,6 +95,8 @@ cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSiz
     if (p->C < 1) return fail(CNG_EINVAL, "C=%d must be >= 1", p->C);
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(CNG_EINVAL, "alpha must be finite and > 0");
     if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(CNG_EINVAL, "tau must be finite and >= 0");
+    s = check_adaptive(p->alpha, p->alpha_max, p->alpha_step);
+    if (s != CNG_OK) return s;
     if (p->Lc < 0) return fail(CNG_EINVAL, "Lc=%d must be >= 0", p->Lc);
     if (p->band < 0 || p->band > 512) return fail(CNG_EUNSUPPORTED, "band=%d must be in [0, 512]", p->band);
     if (p->visited_log2 != 0 && (p->visited_log2 < 6 || p->visited_log2 > 14))
@@ -169,7 +180,8 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
     if (e != hipSuccess) return hip_fail(e, "candidates");
     const double t2 = now_ms();
 
-    e = cng::launch_prune(points, n, d, cand, candD, z.Ceff, p->R, z.W, p->alpha, p->tau, adj, st);
+    e = cng::launch_prune(points, n, d, cand, candD, z.Ceff, p->R, z.W, p->alpha, p->tau, adj, st, 0,
+                          p->alpha_max, p->alpha_step);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "prune");
     const double t3 = now_ms();
@@ -177,8 +189,8 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
     // phase 3: the candidate arrays (n x Ceff) are free again and hold the
     // candidate sets of the backward-edge phase
     if (p->flags & CNG_BUILD_BACKWARD) {
-        e = cng::run_backward(points, n, d, adj, z.W, p->R, z.Ceff, p->alpha, p->tau, cand, candD,
-                              scratch, st);
+        e = cng::run_backward(points, n, d, adj, z.W, p->R, z.Ceff, p->alpha, p->alpha_max,
+                              p->alpha_step, p->tau, cand, candD, scratch, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "backward edges");
     }
@@ -288,8 +300,8 @@ cng_status cng_backward_workspace_size(int64_t n, int32_t W, int32_t Cb, size_t 
 }
 
 cng_status cng_backward(const float *points, int64_t n, int32_t d, uint32_t *adj, int32_t W,
-                        int32_t R, int32_t Cb, double alpha, double tau, void *workspace,
-                        size_t ws_bytes, void *stream)
+                        int32_t R, int32_t Cb, double alpha, double alpha_max, double alpha_step,
+                        double tau, void *workspace, size_t ws_bytes, void *stream)
 {
     cng_status s = check_points(points, n, d, 1);
     if (s != CNG_OK) return s;
@@ -300,14 +312,37 @@ cng_status cng_backward(const float *points, int64_t n, int32_t d, uint32_t *adj
     if (R < 1 || R > W) return fail(CNG_EINVAL, "need 1 <= R <= W");
     if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(CNG_EINVAL, "alpha must be finite and > 0");
     if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(CNG_EINVAL, "tau must be finite and >= 0");
+    s = check_adaptive(alpha, alpha_max, alpha_step);
+    if (s != CNG_OK) return s;
     if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     unsigned char *w = (unsigned char *)workspace;
     uint32_t *cand = (uint32_t *)w;
     float *candD = (float *)(w + align256((size_t)n * Cb * 4));
     void *rest = w + align256((size_t)n * Cb * 4) * 2;
-    hipError_t e = cng::run_backward(points, n, d, adj, W, R, Cb, alpha, tau, cand, candD, rest,
-                                     (hipStream_t)stream);
+    hipError_t e = cng::run_backward(points, n, d, adj, W, R, Cb, alpha, alpha_max, alpha_step, tau,
+                                     cand, candD, rest, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "backward edges");
+    return ok();
+}
+
+cng_status cng_prune_adaptive(const float *points, int64_t n, int32_t d, const uint32_t *cand,
+                              const float *candD, int32_t C, int32_t R, int32_t W, double alpha0,
+                              double alpha_max, double alpha_step, double tau, uint32_t *adj,
+                              void *stream)
+{
+    if (!(alpha_step > 0.0)) return fail(CNG_EINVAL, "alpha_step must be > 0");
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (!cand || !candD || !adj) return fail(CNG_EINVAL, "NULL array argument");
+    if (C < 1 || R < 1 || W < R) return fail(CNG_EINVAL, "need C >= 1, R >= 1, W >= R");
+    if (W > MAX_W) return fail(CNG_EUNSUPPORTED, "W=%d exceeds %d", W, MAX_W);
+    if (!(alpha0 > 0.0) || !std::isfinite(alpha0)) return fail(CNG_EINVAL, "alpha0 must be finite and > 0");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(CNG_EINVAL, "tau must be finite and >= 0");
+    s = check_adaptive(alpha0, alpha_max, alpha_step);
+    if (s != CNG_OK) return s;
+    hipError_t e = cng::launch_prune(points, n, d, cand, candD, C, R, W, alpha0, tau, adj,
+                                     (hipStream_t)stream, 0, alpha_max, alpha_step);
+    if (e != hipSuccess) return hip_fail(e, "prune");
     return ok();
 }
 

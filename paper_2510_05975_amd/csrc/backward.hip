@@ -3,9 +3,9 @@
 // Every edge (u, v) of the pruned graph adds the reverse edge (v, u).  The
 // candidate set of a point p is its out-neighbours together with the sources
 // of the edges into it (a set), ordered by (D, id) and cut to its Cb nearest;
-// if it holds more than R points it is pruned once (Algorithm 2 with cap R),
-// otherwise it becomes p's row as it is.  Every decision reads the graph as it
-// was before the phase.
+// if it holds more than R points it is pruned once (Algorithm 2 with cap R, or
+// Algorithm 4 with adaptive alpha), otherwise it becomes p's row as it is.
+// Every decision reads the graph as it was before the phase.
 //
 // Device steps: in-degrees (atomics), an exclusive scan into offsets, the
 // sources scattered into per-point lists (their order within a list is free:
@@ -270,8 +270,8 @@ size_t backward_workspace_bytes(int64_t n, int W)
 }
 
 hipError_t run_backward(const float *points, int64_t n, int d, uint32_t *adj, int W, int R, int Cb,
-                        double alpha, double tau, uint32_t *cand, float *candD, void *ws,
-                        hipStream_t stream)
+                        double alpha, double alpha_max, double alpha_step, double tau,
+                        uint32_t *cand, float *candD, void *ws, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
     unsigned char *w = (unsigned char *)ws;
@@ -306,7 +306,8 @@ hipError_t run_backward(const float *points, int64_t n, int d, uint32_t *adj, in
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // rows are rewritten only after every candidate set has been read from them
-    return launch_prune(points, n, d, cand, candD, Cb, R, W, alpha, tau, adj, stream, R);
+    return launch_prune(points, n, d, cand, candD, Cb, R, W, alpha, tau, adj, stream, R, alpha_max,
+                        alpha_step);
 }
 
 }  // namespace cng

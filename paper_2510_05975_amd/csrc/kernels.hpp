@@ -82,17 +82,20 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
                       hipStream_t stream, int64_t *overflow_rows, int *exact_int, int *dtype);
 
 // pruning; with copy_upto > 0 a list of at most copy_upto candidates becomes
-// the row unpruned
+// the row unpruned; alpha_step > 0: adaptive alpha (Algorithm 4) from alpha to
+// alpha_max
 hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *cand,
                         const float *candD, int C, int R, int W, double alpha, double tau,
-                        uint32_t *adj, hipStream_t stream, int copy_upto = 0);
+                        uint32_t *adj, hipStream_t stream, int copy_upto = 0,
+                        double alpha_max = 0.0, double alpha_step = 0.0);
+int adaptive_iters(double alpha0, double alpha_max, double alpha_step);
 
 // backward edges with lazy pruning (Algorithm 3, phase 3); cand / candD hold
 // n x Cb entries of scratch
 size_t backward_workspace_bytes(int64_t n, int W);
 hipError_t run_backward(const float *points, int64_t n, int d, uint32_t *adj, int W, int R, int Cb,
-                        double alpha, double tau, uint32_t *cand, float *candD, void *ws,
-                        hipStream_t stream);
+                        double alpha, double alpha_max, double alpha_step, double tau,
+                        uint32_t *cand, float *candD, void *ws, hipStream_t stream);
 
 // connectivity
 size_t connect_workspace_bytes(int64_t n, int W, int Lc);

@@ -12,6 +12,8 @@
 // shortcut set, since a decision only looks at earlier kept points).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -29,6 +31,10 @@ struct PruneArgs {
     double alpha, tau;
     uint32_t *adj;
     int copy_upto;  // > 0: a list of at most this many candidates is copied, not pruned
+    // Algorithm 4: passes i = 0 .. iters-1 with alpha_i = alpha + i * alpha_step;
+    // the first whose kept set reaches R/2 stands (iters = 1: fixed alpha)
+    int iters;
+    double alpha_step;
 };
 
 template <int G, int RND, bool VEC>
@@ -72,11 +78,15 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
         }
         return;
     }
-    const float al = (float)a.alpha, ta = (float)a.tau;
-    const float cterm = (al + 1.0f) * ta;
+    const float ta = (float)a.tau;
     const float *xp = a.points + (size_t)p * d;
 
     int ns = 0;
+    for (int it = 0; it < a.iters; ++it) {
+    const double alpha = a.iters > 1 ? a.alpha + it * a.alpha_step : a.alpha;
+    const float al = (float)alpha;
+    const float cterm = (al + 1.0f) * ta;
+    ns = 0;
     for (int j = 0; j < a.C && ns < a.R; ++j) {
         const uint32_t u = a.cand[(size_t)p * a.C + j];
         if (u == NONE || (int64_t)u >= a.n) break;
@@ -119,8 +129,8 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
                         const float *xv = a.points + (size_t)S[c] * d;
                         double a64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xp, xu, d, gl));
                         double b64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xu, xv, d, gl));
-                        double ab64 = a.alpha * b64;
-                        double c64 = (a.alpha + 1.0) * a.tau;
+                        double ab64 = alpha * b64;
+                        double c64 = (alpha + 1.0) * a.tau;
                         dec = a64 > ab64 + c64;
                     } else {
                         dec = lhs > rhs;
@@ -136,6 +146,8 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
             wave_sync();
             ++ns;
         }
+    }
+    if (2 * ns >= a.R) break;
     }
     uint32_t *out = a.adj + (size_t)p * a.W;
     for (int s = lane; s < a.W; s += 64) out[s] = s < ns ? S[s] : NONE;
@@ -166,12 +178,21 @@ PruneFn pick_prune(int d)
 
 }  // namespace
 
+int adaptive_iters(double alpha0, double alpha_max, double alpha_step)
+{
+    if (!(alpha_step > 0.0)) return 1;
+    return (int)std::floor((alpha_max - alpha0) / alpha_step + 1e-9) + 1;
+}
+
 hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *cand,
                         const float *candD, int C, int R, int W, double alpha, double tau,
-                        uint32_t *adj, hipStream_t stream, int copy_upto)
+                        uint32_t *adj, hipStream_t stream, int copy_upto, double alpha_max,
+                        double alpha_step)
 {
     if (n == 0) return hipSuccess;
-    PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj, copy_upto};
+    const int iters = adaptive_iters(alpha, alpha_max, alpha_step);
+    PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj, copy_upto, iters,
+                alpha_step};
     const bool vec = (d % 4 == 0) && ((uintptr_t)points % 16 == 0);
     PruneFn fn = vec ? pick_prune<true>(d) : pick_prune<false>(d);
     const int wpb = 4;

@@ -18,14 +18,17 @@ def test_exports_every_declared_symbol():
 
 
 def _params(**kw):
-    p = dict(R=32, extra=1, C=128, alpha=1.2, tau=0.0, flags=1, Lc=0, band=0, visited_log2=0)
+    p = dict(R=32, extra=1, C=128, alpha=1.2, tau=0.0, flags=1, Lc=0, band=0, visited_log2=0,
+             alpha_max=1.2, alpha_step=0.0)
     p.update(kw)
     return _lib.BuildParams(*[p[f] for f, _ in _lib.BuildParams._fields_])
 
 
 @pytest.mark.parametrize("bad", [dict(R=0), dict(extra=-1), dict(C=0), dict(alpha=0.0),
                                  dict(alpha=float("nan")), dict(tau=-1.0), dict(Lc=-1),
-                                 dict(visited_log2=3), dict(visited_log2=20)])
+                                 dict(visited_log2=3), dict(visited_log2=20),
+                                 dict(alpha_step=-0.05), dict(alpha_step=0.05, alpha_max=1.0),
+                                 dict(alpha_step=0.05, alpha_max=float("inf"))])
 def test_build_params_rejected(bad):
     nb = C.c_size_t(0)
     st = cng.lib().cng_build_workspace_size(1000, 32, C.byref(_params(**bad)), C.byref(nb))
@@ -33,7 +36,8 @@ def test_build_params_rejected(bad):
     assert cng.lib().cng_last_error().decode() != ""
 
 
-@pytest.mark.parametrize("bad", [dict(R=200, extra=100), dict(band=1024), dict(C=300), dict(Lc=1000)])
+@pytest.mark.parametrize("bad", [dict(R=200, extra=100), dict(band=1024), dict(C=300), dict(Lc=1000),
+                                 dict(alpha_step=1e-6, alpha_max=2.0)])
 def test_build_params_unsupported(bad):
     nb = C.c_size_t(0)
     st = cng.lib().cng_build_workspace_size(100000, 32, C.byref(_params(**bad)), C.byref(nb))
