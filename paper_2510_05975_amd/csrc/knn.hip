@@ -2,10 +2,12 @@
 // D in the fixed reduction order.  This stands in for the local-neighbour set
 // V of Algorithm 3 (phases 1-2), computed exactly.
 //
-// Stage 1, filter (MFMA): a workgroup owns 128 rows and sweeps all column
-// tiles of 128.  For each pair it computes F = |y|^2 - 2 x.y on the matrix
+// Stage 1, filter (MFMA): a workgroup owns a block of rows and sweeps all
+// column tiles.  For each pair it computes F = |y|^2 - 2 x.y on the matrix
 // cores (float32 accumulate) and appends (F, id) to the row's band when F is at
-// most the row threshold.  Whenever a band could overflow on the next tile it
+// most the row threshold.  Three forms: bf16 inputs for small-integer data
+// (exact), bf16 hi/lo pairs for other data with d <= 128 (three products per
+// k step), float32 inputs otherwise.  Whenever a band could overflow on the next tile it
 // is compacted: sorted, and cut to F <= F_C + 2E where F_C is the C-th smallest
 // F so far and E bounds |F - (D - |x|^2)| for every column of this row (the
 // product and norm rounding of the filter plus the rounding of D itself).  Any
@@ -439,10 +441,27 @@ __global__ void to_bf16_padded(const float *__restrict__ x, int64_t n, int d, in
     out[t] = k < d ? to_bf16_rne(x[(size_t)r * d + k]) : (uint16_t)0;
 }
 
+// x [n x d] float32 -> hi = bf16(x), lo = bf16(x - hi), [n x K] each, zero padded
+// (x - hi is exact in float32)
+__global__ void to_bf16_split(const float *__restrict__ x, int64_t n, int d, int K,
+                              uint16_t *__restrict__ hi, uint16_t *__restrict__ lo)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * K) return;
+    int64_t r = t / K;
+    int k = (int)(t % K);
+    const float v = k < d ? x[(size_t)r * d + k] : 0.f;
+    const uint16_t h = to_bf16_rne(v);
+    hi[t] = h;
+    lo[t] = to_bf16_rne(v - __uint_as_float((uint32_t)h << 16));
+}
+
 struct FilterBf16Args {
     FilterArgs f;
-    const uint16_t *rows16;  // [nr x K]
-    const uint16_t *cols16;  // [nc x K]
+    const uint16_t *rows16;    // [nr x K]
+    const uint16_t *cols16;    // [nc x K]
+    const uint16_t *rows16lo;  // split mode: bf16 of x - hi, [nr x K]
+    const uint16_t *cols16lo;  // [nc x K]
 };
 
 // LDS-only barrier: the band stores of the epilogue need not be complete here
@@ -454,16 +473,21 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// SPLIT (general float data): every value is the sum of two bf16 numbers,
+// hi = bf16(x) and lo = bf16(x - hi), and x.y is taken as hi.hi + hi.lo + lo.hi
+// on the matrix cores (the dropped parts are below 3.1 * 2^-16 |x_k||y_k| per
+// element; the band margin E accounts for them).
+template <int KS, bool SPLIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPLIT ? 1 : 2, SPLIT ? 1 : 2)))
 void filter_bf16(FilterBf16Args A)
 {
     constexpr int K = 16 * KS;
     constexpr int BSTR = K + 8;  // bf16 elements per LDS column row (16 B pad: no bank conflicts)
+    constexpr int NP = SPLIT ? 2 : 1;  // parts per value in LDS: hi (and lo)
     const FilterArgs &a = A.f;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);              // 2 x BN2 x BSTR
-    float *nys = reinterpret_cast<float *>(Bs + 2 * BN2 * BSTR);    // 2 x BN2 column norms
+    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);                 // 2 x NP x BN2 x BSTR
+    float *nys = reinterpret_cast<float *>(Bs + 2 * NP * BN2 * BSTR);  // 2 x BN2 column norms
     float *thr = nys + 2 * BN2;                                     // BM2
     float *erow = thr + BM2;
     int *cnt = reinterpret_cast<int *>(erow + BM2);                // band counts, during compaction
@@ -488,22 +512,24 @@ void filter_bf16(FilterBf16Args A)
     // 64 rows, so these live in a register, read and written per row by lane
     // index, and go through LDS (as counts) only around compactions.
     const uint32_t rowstart = (uint32_t)(blockIdx.x * BM2 + wave * 64 + lane) * (uint32_t)a.CB;
+    // an overflowed row (threshold -inf) keeps this marker until the end
+    constexpr uint32_t OVERFLOWED = 0xFFFFFFFFu;
     // compaction once a band could not take another whole tile (measured: an
     // earlier cut, at half the capacity, costs more than the appends it saves)
     const int trig = a.CB - BN2;
     uint32_t mypos = rowstart;
 
-    // A fragments of this wave's 64 rows: [row block][k step]
-    bf16x8 af[2][KS];
+    // A fragments of this wave's 64 rows: [row block][k step] (hi, and lo)
+    bf16x8 af[2][KS], al[2][SPLIT ? KS : 1];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int64_t gi = row0 + wave * 64 + i * 32 + (lane & 31);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            if (gi < rend)
-                af[i][ks] = *reinterpret_cast<const bf16x8 *>(A.rows16 + (size_t)gi * K + ks * 16 + (lane >> 5) * 8);
-            else
-                af[i][ks] = bf16x8{};
+            const size_t o = (size_t)gi * K + ks * 16 + (lane >> 5) * 8;
+            af[i][ks] = gi < rend ? *reinterpret_cast<const bf16x8 *>(A.rows16 + o) : bf16x8{};
+            if constexpr (SPLIT)
+                al[i][ks] = gi < rend ? *reinterpret_cast<const bf16x8 *>(A.rows16lo + o) : bf16x8{};
         }
     }
 
@@ -516,7 +542,7 @@ void filter_bf16(FilterBf16Args A)
     // Loads are unconditional (columns past the end are clamped to the last
     // one; their F is NaN through the norm), so no register is cleared while
     // a load may be in flight.
-    u32x4 pre[PER_T];
+    u32x4 pre[NP][PER_T];
     float pny = 0.f;
     bool pdead = false;
     auto fetch = [&](int64_t col0) {
@@ -526,7 +552,9 @@ void filter_bf16(FilterBf16Args A)
             const int col = c / (K / 8), kc = c % (K / 8);
             int64_t gj = col0 + col;
             gj = gj < a.nc ? gj : a.nc - 1;
-            pre[i] = *reinterpret_cast<const u32x4 *>(A.cols16 + (size_t)gj * K + kc * 8);
+            pre[0][i] = *reinterpret_cast<const u32x4 *>(A.cols16 + (size_t)gj * K + kc * 8);
+            if constexpr (SPLIT)
+                pre[NP - 1][i] = *reinterpret_cast<const u32x4 *>(A.cols16lo + (size_t)gj * K + kc * 8);
         }
         if (threadIdx.x < BN2) {
             const int64_t gj = col0 + threadIdx.x;
@@ -536,11 +564,14 @@ void filter_bf16(FilterBf16Args A)
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < PER_T; ++i) {
-            const int c = threadIdx.x + 256 * i;
-            const int col = c / (K / 8), kc = c % (K / 8);
-            *reinterpret_cast<u32x4 *>(Bs + (size_t)buf * BN2 * BSTR + col * BSTR + kc * 8) = pre[i];
-        }
+        for (int part = 0; part < NP; ++part)
+#pragma unroll
+            for (int i = 0; i < PER_T; ++i) {
+                const int c = threadIdx.x + 256 * i;
+                const int col = c / (K / 8), kc = c % (K / 8);
+                *reinterpret_cast<u32x4 *>(Bs + ((size_t)buf * NP + part) * BN2 * BSTR + col * BSTR +
+                                           kc * 8) = pre[part][i];
+            }
         if (threadIdx.x < BN2) nys[buf * BN2 + threadIdx.x] = pdead ? __builtin_nanf("") : pny;
     };
 
@@ -569,23 +600,45 @@ void filter_bf16(FilterBf16Args A)
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-        const uint16_t *Bb = Bs + (size_t)buf * BN2 * BSTR + (lane & 31) * BSTR + (lane >> 5) * 8;
+        const uint16_t *Bb = Bs + (size_t)buf * NP * BN2 * BSTR + (lane & 31) * BSTR + (lane >> 5) * 8;
+        const uint16_t *Bl = Bb + (NP - 1) * BN2 * BSTR;  // lo part (split mode)
         // B fragments one k step ahead of the matrix instructions
         bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bb);
         bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bb + 32 * BSTR);
+        bf16x8 l0 = b0, l1 = b1;
+        if constexpr (SPLIT) {
+            l0 = *reinterpret_cast<const bf16x8 *>(Bl);
+            l1 = *reinterpret_cast<const bf16x8 *>(Bl + 32 * BSTR);
+        }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            bf16x8 n0 = b0, n1 = b1;
+            bf16x8 n0 = b0, n1 = b1, m0 = l0, m1 = l1;
             if (ks + 1 < KS) {
                 n0 = *reinterpret_cast<const bf16x8 *>(Bb + (ks + 1) * 16);
                 n1 = *reinterpret_cast<const bf16x8 *>(Bb + 32 * BSTR + (ks + 1) * 16);
+                if constexpr (SPLIT) {
+                    m0 = *reinterpret_cast<const bf16x8 *>(Bl + (ks + 1) * 16);
+                    m1 = *reinterpret_cast<const bf16x8 *>(Bl + 32 * BSTR + (ks + 1) * 16);
+                }
             }
             acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], b0, acc[0][0], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], b0, acc[1][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], b1, acc[0][1], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], b1, acc[1][1], 0, 0, 0);
+            if constexpr (SPLIT) {
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], l0, acc[0][0], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], l0, acc[1][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], l1, acc[0][1], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], l1, acc[1][1], 0, 0, 0);
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0][ks], b0, acc[0][0], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1][ks], b0, acc[1][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0][ks], b1, acc[0][1], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1][ks], b1, acc[1][1], 0, 0, 0);
+            }
             b0 = n0;
             b1 = n1;
+            l0 = m0;
+            l1 = m1;
         }
         // next tile into the other buffer now: its loads were issued a whole
         // matrix phase ago, and waiting for them later would also wait for the
@@ -637,7 +690,7 @@ void filter_bf16(FilterBf16Args A)
         lds_barrier();
         const bool last = !more;
         if (flag[0] || last) {
-            cnt[wave * 64 + lane] = (int)(mypos - rowstart);
+            cnt[wave * 64 + lane] = mypos == OVERFLOWED ? -1 : (int)(mypos - rowstart);
             __syncthreads();  // band stores and counts of every wave complete
             for (int li = wave; li < BM2; li += 4) {
                 const int c = cnt[li];
@@ -650,7 +703,7 @@ void filter_bf16(FilterBf16Args A)
             if (threadIdx.x == 0) flag[0] = 0;
             {
                 const int c = cnt[wave * 64 + lane];  // -1: overflowed, takes nothing more
-                mypos = rowstart + (uint32_t)(c > 0 ? c : 0);
+                mypos = c < 0 ? OVERFLOWED : rowstart + (uint32_t)c;
             }
             load_thr();
             __syncthreads();
@@ -666,10 +719,10 @@ void filter_bf16(FilterBf16Args A)
     }
 }
 
-size_t filter_bf16_lds_bytes(int K, int CB)
+size_t filter_bf16_lds_bytes(int K, int CB, bool split)
 {
-    return (size_t)2 * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 + (size_t)BM2 * 4 * 3 + 16 +
-           (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
+    return (size_t)2 * (split ? 2 : 1) * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 +
+           (size_t)BM2 * 4 * 3 + 16 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
 }
 
 // ---------------------------------------------------------------- rerank
@@ -889,9 +942,9 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
     p.chunk_rows = chunk;
     p.bytes = align256((size_t)nc * 4) + align256((size_t)nr * 4) * 2 + align256(sizeof(PrepOut)) +
               align256((size_t)chunk * CB * 4) * 2 + align256((size_t)chunk * 4);
-    if (d <= 128) {  // bf16 copies for the exact small-integer filter
+    if (d <= 128) {  // bf16 copies (hi and lo parts) for the matrix-core filters
         const int K = (d + 31) / 32 * 32;
-        p.bytes += align256((size_t)nc * K * 2) + align256((size_t)nr * K * 2);
+        p.bytes += (align256((size_t)nc * K * 2) + align256((size_t)nr * K * 2)) * 2;
     }
     return p;
 }
@@ -917,11 +970,15 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     int *cnt = (int *)w;
     w += align256((size_t)plan.chunk_rows * 4);
     const int K16 = (d + 31) / 32 * 32;  // bf16 row length: whole k steps of 16, an even count
-    uint16_t *cols16 = nullptr, *rows16 = nullptr;
+    uint16_t *cols16 = nullptr, *rows16 = nullptr, *cols16lo = nullptr, *rows16lo = nullptr;
     if (d <= 128) {
         cols16 = (uint16_t *)w;
         w += align256((size_t)nc * K16 * 2);
         rows16 = (uint16_t *)w;
+        w += align256((size_t)nr * K16 * 2);
+        cols16lo = (uint16_t *)w;
+        w += align256((size_t)nc * K16 * 2);
+        rows16lo = (uint16_t *)w;
     }
 
     hipLaunchKernelGGL(init_prep, dim3(1), dim3(1), 0, stream, st);
@@ -942,19 +999,36 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
                  (h.any_neg ? 4.0 * d * M * M <= lim : 2.0 * d * M * M <= lim);
     // bf16 holds every integer of magnitude <= 256 exactly
     const bool use_bf16 = exact && d <= 128 && M <= 256.0;
+    // other data with d <= 128: hi / lo bf16 parts, three products per k step
+    const bool use_split = !use_bf16 && !exact && d <= 128;
     if (exact_int) *exact_int = exact ? 1 : 0;
-    if (dtype) *dtype = use_bf16 ? 1 : 0;
-    if (use_bf16) {
+    if (dtype) *dtype = use_bf16 ? 1 : use_split ? 2 : 0;
+    const bool self = rows == cols && nr == nc;
+    if (use_bf16 || use_split) {
         const int64_t tc = nc * K16, tr = nr * K16;
-        hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, stream,
-                           cols, nc, d, K16, cols16);
-        if (rows != cols || nr != nc)
-            hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tr + 255) / 256)), dim3(256), 0,
-                               stream, rows, nr, d, K16, rows16);
-        else
+        if (use_bf16) {
+            hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0,
+                               stream, cols, nc, d, K16, cols16);
+            if (!self)
+                hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tr + 255) / 256)), dim3(256), 0,
+                                   stream, rows, nr, d, K16, rows16);
+        } else {
+            hipLaunchKernelGGL(to_bf16_split, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0,
+                               stream, cols, nc, d, K16, cols16, cols16lo);
+            if (!self)
+                hipLaunchKernelGGL(to_bf16_split, dim3((unsigned)((tr + 255) / 256)), dim3(256), 0,
+                                   stream, rows, nr, d, K16, rows16, rows16lo);
+        }
+        if (self) {
             rows16 = cols16;
+            rows16lo = cols16lo;
+        }
     }
-    const double kappa = (6.0 * d + 40.0) * 5.9604644775390625e-8;  // (6d + 40) * 2^-24
+    // E = kappa (|x| + max|y|)^2 bounds |F - (D - |x|^2)| (module comment).  The
+    // split filter adds 2d more float32 roundings per pair and the dropped
+    // lo.lo and rounding parts of the bf16 pairs (< 3.1 * 2^-16 |x||y|).
+    const double kappa = use_split ? (12.0 * d + 40.0) * 5.9604644775390625e-8 + 4.0 * 1.52587890625e-5
+                                   : (6.0 * d + 40.0) * 5.9604644775390625e-8;  // (6d + 40) * 2^-24
     hipLaunchKernelGGL(row_bounds, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, xn, nr,
                        st, kappa, exact ? 1 : 0, E);
 
@@ -967,15 +1041,24 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     for (int64_t r0 = 0; r0 < nr; r0 += plan.chunk_rows) {
         const int64_t chunk = nr - r0 < plan.chunk_rows ? nr - r0 : plan.chunk_rows;
         FilterArgs fa{rows, nr, r0, chunk, cols, nc, d, C, exclude_self, ny, E, CB, bandF, bandI, cnt, st};
-        if (use_bf16) {
-            FilterBf16Args fb{fa, rows16, cols16};
+        if (use_bf16 || use_split) {
+            FilterBf16Args fb{fa, rows16, cols16, rows16lo, cols16lo};
             const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
-            const unsigned lds = (unsigned)filter_bf16_lds_bytes(K16, CB);
-            switch (K16 / 32) {
-            case 1: hipLaunchKernelGGL(filter_bf16<2>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 2: hipLaunchKernelGGL(filter_bf16<4>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            case 3: hipLaunchKernelGGL(filter_bf16<6>, dim3(blocks), dim3(256), lds, stream, fb); break;
-            default: hipLaunchKernelGGL(filter_bf16<8>, dim3(blocks), dim3(256), lds, stream, fb); break;
+            const unsigned lds = (unsigned)filter_bf16_lds_bytes(K16, CB, use_split);
+            if (use_split) {
+                switch (K16 / 32) {
+                case 1: hipLaunchKernelGGL((filter_bf16<2, true>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                case 2: hipLaunchKernelGGL((filter_bf16<4, true>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                case 3: hipLaunchKernelGGL((filter_bf16<6, true>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                default: hipLaunchKernelGGL((filter_bf16<8, true>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                }
+            } else {
+                switch (K16 / 32) {
+                case 1: hipLaunchKernelGGL((filter_bf16<2, false>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                case 2: hipLaunchKernelGGL((filter_bf16<4, false>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                case 3: hipLaunchKernelGGL((filter_bf16<6, false>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                default: hipLaunchKernelGGL((filter_bf16<8, false>), dim3(blocks), dim3(256), lds, stream, fb); break;
+                }
             }
         } else {
             const unsigned fblocks = (unsigned)((chunk + BM - 1) / BM);

@@ -64,12 +64,16 @@ def test_knn_dims(d):
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
 
 
-def test_knn_forced_band_overflow():
-    """A band too small for the candidates sends rows to the exhaustive path."""
-    x, _ = workloads.generate(1, n=3000, nq=1)
-    ids, D, ovf = gpu_knn(x, x, 64, True, band=64)
-    assert ovf > 0
-    oids, oD = oracle.knn(x, x, 64, exclude_self=True)
+@pytest.mark.parametrize("cfg,C,band", [(1, 64, 64), (2, 64, 64), (3, 64, 64), (4, 64, 64),
+                                       (2, 128, 256), (4, 128, 256)])
+def test_knn_forced_band_overflow(cfg, C, band):
+    """A band too small for the candidates sends rows to the exhaustive path
+    (every filter form: float32, bf16 small-integer, bf16 hi/lo pairs)."""
+    x, _ = workloads.generate(cfg, n=3000 if cfg != 3 else 1200, nq=1)
+    ids, D, ovf = gpu_knn(x, x, C, True, band=band)
+    if band <= C:
+        assert ovf > 0
+    oids, oD = oracle.knn(x, x, C, exclude_self=True)
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
 
 
