@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--learn-vmf", action="store_true", help="also run the learned entry on the vMF workload")
     ap.add_argument("--learn-train", type=int, default=200_000, help="training queries of the learned-entry leg")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-qps", type=str, default="50000,200000")
+    ap.add_argument("--serve-qps", type=str, default="5000,50000,200000")
     return ap.parse_args()
 
 

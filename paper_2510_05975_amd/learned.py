@@ -1,6 +1,7 @@
 """Learned entry point: k-means entry nodes, labels from the plain search,
 MLP training and gated prediction.  This module only sequences library calls;
-every computation runs in libcng's kernels.  Random draws (initial weights,
+every computation runs in libcng's kernels, except the input standardisation
+of training (a mean and a scale, folded into the first layer afterwards).  Random draws (initial weights,
 k-means seeds, epoch permutations) come from numpy generators on the host and
 are passed in as inputs."""
 from __future__ import annotations
@@ -51,10 +52,21 @@ def kmeans_entries(points: torch.Tensor, K: int, iters: int = 20, seed: int = 1)
 
 
 def train(model: EntryModel, X: torch.Tensor, labels: torch.Tensor, epochs: int = 4,
-          batch: int = 1024, lr: float = 1e-3, seed: int = 2, log_every: int = 0):
-    """Adam on mini-batches drawn by a seeded permutation per epoch."""
+          batch: int = 1024, lr: float = 1e-3, seed: int = 2, log_every: int = 0,
+          standardize: bool = True):
+    """Adam on mini-batches drawn by a seeded permutation per epoch.
+
+    With ``standardize`` the network is trained on (X - mu) / s (mu the mean
+    query, s the root-mean-square deviation), and the affine map is then folded
+    into the first layer (W1 / s, b1 - mu W1 / s), so that prediction takes raw
+    queries.  Data of large magnitude (e.g. integers in [0, 255]) does not train
+    otherwise."""
     n = X.shape[0]
     dev = X.device
+    if standardize:
+        mu = X.mean(0)
+        sc = float((X - mu).pow(2).mean().sqrt().clamp_min(1e-12))
+        X = ((X - mu) / sc).contiguous()
     P = model.params
     G = torch.empty_like(P)
     m1 = torch.zeros_like(P)
@@ -74,4 +86,10 @@ def train(model: EntryModel, X: torch.Tensor, labels: torch.Tensor, epochs: int 
             if log_every and step % log_every == 0:
                 model.history.append((step, float(loss.item())))
         model.history.append((step, float(loss.item())))
+    if standardize:
+        d, H = model.d, model.H
+        W1 = P[: d * H].view(d, H)
+        b1 = P[d * H: d * H + H]
+        b1 -= (mu / sc) @ W1
+        W1 /= sc
     return model

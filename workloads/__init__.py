@@ -35,7 +35,7 @@ CONFIGS = {
     2: dict(name="sift_like_1m", gen="sift_like", n=1_000_000, d=128, nq=10_000, C=128, R=32,
             alpha=1.2, tau=0.0, k=10, L=[16, 24, 32, 48, 64, 96, 128, 192, 256]),
     3: dict(name="gist_like_1m", gen="gist_like", n=1_000_000, d=960, nq=1_000, C=192, R=48,
-            alpha=1.2, tau=0.0, k=10, L=[16, 24, 32, 48, 64, 96, 128, 192, 256]),
+            alpha=1.2, tau=0.0, k=10, L=[16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512]),
     4: dict(name="vmf_10m", gen="vmf", n=10_000_000, d=96, nq=10_000, C=128, R=32,
             alpha=1.2, tau=0.0, k=10, L=[32, 48, 64, 96, 128, 192, 256, 384, 512]),
     5: dict(name="sift_like_10m", gen="sift_like", n=10_000_000, d=128, nq=10_000, C=128, R=32,
