@@ -107,3 +107,71 @@ def test_search_quantized_sampled_full(full, dtype):
                                           full["g"].entry)
     assert (ids[qs] == oids).all()
     assert same_f32(dists[qs], f32_of(od))
+
+
+def test_adaptive_and_backward_sampled_full(full):
+    """The paper's alpha-CNG stages at full size: adaptive pruning (Algorithm 4)
+    on sampled rows against the oracle, the backward-edge phase on sampled rows
+    against its definition (own row plus in-edge sources, by (D, id), cut to C,
+    pruned adaptively when longer than R), connectivity in full, and sampled
+    searches on the finished graph."""
+    x, rows = full["x"], full["rows"]
+    n = len(x)
+    A0, AMAX, STEP = 0.9, 1.6, 0.05
+    print("fullscale: adaptive prune + backward on the GPU", flush=True)
+    ids_t, D_t, _ = cng.knn(full["xd"], full["xd"], C, exclude_self=True)
+    p2_t = cng.prune(full["xd"], ids_t, D_t, R, A0, 0.0, width=R + 1, alpha_max=AMAX,
+                     alpha_step=STEP)
+    p3_t = p2_t.clone()
+    cng.backward(full["xd"], p3_t, R, C, A0, 0.0, alpha_max=AMAX, alpha_step=STEP)
+    torch.cuda.synchronize()
+    ids, D = host_ids(ids_t), D_t.cpu().numpy()
+    p2, p3 = host_ids(p2_t), host_ids(p3_t)
+    del ids_t, D_t, p2_t, p3_t
+
+    def oracle_rows(cands):
+        """Adaptive pruning of the given candidate lists (row -> ids by (D, id))."""
+        width = max(len(v) for v in cands.values())
+        cand = np.full((n, width), oracle.NONE, np.uint32)
+        candD = np.full((n, width), np.inf)
+        for p, v in cands.items():
+            cand[p, : len(v)] = v
+            candD[p, : len(v)] = [oracle.dist_f32(x[p], x[u]) for u in v]
+        return oracle.prune(x, cand, candD, R, A0, width=R + 1, alpha_max=AMAX, alpha_step=STEP)
+
+    # phase 2 on sampled rows (the candidate lists checked in full elsewhere)
+    o2 = oracle_rows({int(p): [int(u) for u in ids[p]] for p in rows})
+    assert (p2[rows] == o2[rows]).all()
+    assert all(float(D[p][j]) == float(np.float32(oracle.dist_f32(x[p], x[ids[p][j]])))
+               for p in rows[:4] for j in range(0, C, 17))
+
+    # phase 3 on sampled rows: own row plus sources of in-edges (a set), by (D, id)
+    valid = p2 != oracle.NONE
+    src_u = np.repeat(np.arange(n, dtype=np.int64), valid.sum(1))
+    dst_v = p2[valid].astype(np.int64)
+    cands, short = {}, {}
+    for p in rows:
+        V = set(int(v) for v in p2[p] if v != oracle.NONE) | set(src_u[dst_v == p].tolist())
+        V = sorted(V, key=lambda u: (float(oracle.dist_f32(x[p], x[u])), u))[:C]
+        (cands if len(V) > R else short)[int(p)] = V
+    if cands:
+        o3 = oracle_rows(cands)
+        for p in cands:
+            assert (p3[p] == o3[p]).all(), p
+    for p, V in short.items():
+        assert [int(v) for v in p3[p] if v != oracle.NONE] == V, p
+
+    # connectivity in full on the GPU's phase-3 graph, against the whole build
+    g = cng.build(full["xd"], R, C, A0, alpha_max=AMAX, alpha_step=STEP, backward=True)
+    torch.cuda.synchronize()
+    gadj = host_ids(g.adj)
+    cadj, added, _ = oracle.connect(x, p3, g.entry, C)
+    assert (gadj == cadj).all() and g.stats["connect_added"] == added
+
+    # sampled searches on the finished graph
+    qs = full["qs"]
+    ids_t, d_t, _, _ = cng.search(full["xd"], g.adj, full["qd"], K, 96, g.entry)
+    torch.cuda.synchronize()
+    oids, od, _, _ = oracle.search(x, gadj, full["q"][qs], K, 96, g.entry)
+    assert (host_ids(ids_t)[qs] == oids).all()
+    assert same_f32(d_t.cpu().numpy()[qs], f32_of(od))
