@@ -59,16 +59,41 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g)
     const int ia = i0 + (lane & 31), jb = j0 + (lane & 31);
     const bool iok = ia < g.M, jok = jb < g.N;
     if (BF16) {
-        for (int k0 = 0; k0 < g.K; k0 += 16) {
-            bf16x8 av, bv;
+        // rows of A contiguous (forward products): two 16-byte loads per lane
+        // and k step; the k loop is unrolled so that the loads of several
+        // steps are in flight together
+        const bool avec = g.rk == nullptr && g.as1 == 1 && (g.K & 15) == 0 && (g.as0 & 3) == 0 &&
+                          ((uintptr_t)g.A & 15) == 0;
+        if (avec) {
+            const float *arow = g.A + (iok ? (g.ri ? (int64_t)g.ri[ia] : ia) * g.as0 : 0);
+#pragma unroll 4
+            for (int k0 = 0; k0 < g.K; k0 += 16) {
+                const int kb = k0 + (lane >> 5) * 8;
+                float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+                if (iok) {
+                    a0 = *reinterpret_cast<const float4 *>(arow + kb);
+                    a1 = *reinterpret_cast<const float4 *>(arow + kb + 4);
+                }
+                bf16x8 av, bv;
+                av[0] = to_bf16(a0.x); av[1] = to_bf16(a0.y); av[2] = to_bf16(a0.z); av[3] = to_bf16(a0.w);
+                av[4] = to_bf16(a1.x); av[5] = to_bf16(a1.y); av[6] = to_bf16(a1.z); av[7] = to_bf16(a1.w);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int k = k0 + (lane >> 5) * 8 + t;
-                const bool kok = k < g.K;
-                av[t] = to_bf16(iok && kok ? g.A[aidx(g, ia, k)] : 0.f);
-                bv[t] = to_bf16(jok && kok ? g.B[k * g.bs0 + jb * g.bs1] : 0.f);
+                for (int t = 0; t < 8; ++t)
+                    bv[t] = to_bf16(jok ? g.B[(int64_t)(kb + t) * g.bs0 + jb * g.bs1] : 0.f);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        } else {
+            for (int k0 = 0; k0 < g.K; k0 += 16) {
+                bf16x8 av, bv;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int k = k0 + (lane >> 5) * 8 + t;
+                    const bool kok = k < g.K;
+                    av[t] = to_bf16(iok && kok ? g.A[aidx(g, ia, k)] : 0.f);
+                    bv[t] = to_bf16(jok && kok ? g.B[k * g.bs0 + jb * g.bs1] : 0.f);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+            }
         }
     } else {
         for (int k0 = 0; k0 < g.K; k0 += 2) {
