@@ -272,6 +272,8 @@ def main():
                                  "traffic": None}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, cng.u32(g.adj), g.entry, k, L, a.cpu_seconds)
+        if not a.search_only:
+            out["cpu_baseline_build"] = cpu_baseline_build(x, R, Cc, alpha, tau, a.cpu_seconds)
     if not a.no_forms and not a.search_only:
         known = {r["L"]: r["recall_tie"] for r in sweep}
 
@@ -602,6 +604,39 @@ def cpu_baseline(x, q, adj, entry, k, L, budget_s):
             "kind": "oracle",
             "sample": f"{m} of the {len(q)} queries x {passes} pass(es), same graph and L, "
                       f"FP32 mode, {dt:.1f}s"}
+
+
+def cpu_baseline_build(x, R, C, alpha, tau, budget_s):
+    """The oracle's candidate stage and pruning on a seeded sample of rows
+    (exact C nearest against all n points, then Algorithm 2), extrapolated to
+    all n rows; the entry point and connectivity phases are not included."""
+    import oracle
+    n = x.shape[0]
+    rng = np.random.Generator(np.random.PCG64(3))
+    m = 64
+    rows = np.sort(rng.choice(n, size=m, replace=False))
+    t = time.perf_counter()
+    oracle.knn(x[rows], x, C + 1)
+    dt = time.perf_counter() - t
+    m = int(min(n, max(m, m * budget_s / max(dt, 1e-3))))
+    rows = np.sort(rng.choice(n, size=m, replace=False))
+    t = time.perf_counter()
+    ids, D = oracle.knn(x[rows], x, C + 1)
+    t_knn = time.perf_counter() - t
+    # drop each row's own column, then prune the sampled rows only
+    cand = np.full((n, C), oracle.NONE, np.uint32)
+    candD = np.full((n, C), np.inf)
+    for j, p in enumerate(rows):
+        keep = ids[j] != p
+        cand[p], candD[p] = ids[j][keep][:C], D[j][keep][:C]
+    t = time.perf_counter()
+    oracle.prune(x, cand, candD, R, alpha, tau, width=R + 1)
+    t_prune = time.perf_counter() - t
+    scale = n / m
+    return {"value": round((t_knn + t_prune) * scale, 1), "unit": "s (extrapolated)",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{m} of {n} rows (seed 3): candidates {t_knn:.1f}s + pruning {t_prune:.1f}s, "
+                      f"x{scale:.0f}; entry point and connectivity not included"}
 
 
 if __name__ == "__main__":
