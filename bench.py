@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16/fp8, learned-entry and serving legs")
     ap.add_argument("--backward", action="store_true",
                     help="build with backward edges and lazy pruning (Algorithm 3, phase 3)")
+    ap.add_argument("--param-sweep", action="store_true",
+                    help="also sweep alpha and tau (fixed alpha) and tau for the adaptive rule: "
+                         "NDC, hops and QPS at recall@10 >= 0.95 per setting")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive-alpha (Algorithm 4) + backward-edge leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
@@ -284,6 +287,8 @@ def main():
             forms[name] = quant_form(cng, torch, x, q, xd, qd, g, dt, gt_ids, gt_dk, k, cfg["L"],
                                      fp32_by_L, a.search_reps)
             print(f"# form {name} {forms[name]}", file=sys.stderr, flush=True)
+        if a.param_sweep:
+            forms["param_sweep"] = param_sweep(cng, torch, xd, qd, gt_ids, gt_dk, cfg, a)
         if not a.no_adaptive:
             forms["adaptive_alpha"] = adaptive_form(cng, torch, xd, qd, gt_ids, gt_dk, cfg, a)
             print(f"# adaptive {forms['adaptive_alpha']}", file=sys.stderr, flush=True)
@@ -378,6 +383,45 @@ def quant_form(cng, torch, x, q, xd, qd, g, dtype, gt_ids, gt_dk, k, Ls, fp32_by
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
             "sweep": sweep}
+
+
+def param_sweep(cng, torch, xd, qd, gt_ids, gt_dk, cfg, a):
+    """The parameter study of the paper (varying alpha, varying tau) on this
+    workload: for every setting, the beam width, NDC, hops and float32 QPS at
+    the first recall@10 >= 0.95, with the build time and mean out-degree."""
+    k = cfg["k"]
+    nq = qd.shape[0]
+    R, C = cfg["R"], cfg["C"]
+    settings = [dict(alpha=al, tau=0.0) for al in (1.0, 1.1, 1.2, 1.3, 1.5, 2.0)]
+    settings += [dict(alpha=1.2, tau=t) for t in (1.0, 4.0, 16.0, 64.0)]
+    settings += [dict(alpha=0.9, tau=t, alpha_max=1.6, alpha_step=0.05, backward=True)
+                 for t in (0.0, 4.0)]
+    rows = []
+    for st in settings:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = cng.build(xd, R, C, st["alpha"], st["tau"], alpha_max=st.get("alpha_max"),
+                      alpha_step=st.get("alpha_step", 0.0), backward=st.get("backward", False))
+        torch.cuda.synchronize()
+        bsec = time.perf_counter() - t0
+
+        def ev(L, g=g):
+            ids, dd, hops, ndc = cng.search(xd, g.adj, qd, k, L, g.entry, visited_log2=14, stats=True)
+            torch.cuda.synchronize()
+            _, tw = recall(cng.u32(ids), gt_ids, gt_dk, dd.cpu().numpy())
+            return dict(L=L, recall_tie=round(tw, 4), hops=round(float(hops.float().mean()), 2),
+                        ndc=round(float(ndc.float().mean()), 1)), None
+
+        row, _, _ = sweep_L(ev, cfg["L"])
+        out = dict(st, build_secs=round(bsec, 3),
+                   mean_degree=round(float((g.adj != -1).sum(1).float().mean()), 2))
+        if row is not None:
+            L = row["L"]
+            ms = timed(torch, lambda: cng.search(xd, g.adj, qd, k, L, g.entry), a.search_reps)
+            out.update(row, qps=round(nq / (ms / 1e3), 1))
+        rows.append(out)
+        print(f"# param {out}", file=sys.stderr, flush=True)
+    return rows
 
 
 def adaptive_form(cng, torch, xd, qd, gt_ids, gt_dk, cfg, a):
