@@ -305,7 +305,7 @@ cng_status cng_nearest_centre_entry(const float *queries, int64_t nq, int32_t d,
  * queries do not all fit in the next free slots; poll completed requests and
  * retry.  Results of a query do not depend on what else is in flight.
  * Rings and results live in coherent pinned host memory.  The grid ends on
- * cng_serve_stop, or by itself after about ten seconds without work (a later
+ * cng_serve_stop, or by itself after several seconds without work (a later
  * poll then reports CNG_EDEVICE).  A server is used from one host thread. */
 typedef struct cng_server cng_server;
 

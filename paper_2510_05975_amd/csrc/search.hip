@@ -412,12 +412,15 @@ __global__ __launch_bounds__(256) void serve_kernel(ServeArgs a)
             // Only the wave holding the oldest unpublished item reads host
             // memory; it copies tail / stop into device memory (mirror[0] /
             // mirror[1]) where the other waves wait without crossing the bus.
-            int state = 0;  // 1: ready, 2: leave
+            int state = 0;  // 1: ready, 2: leave, 3: keep waiting as the poller
             if (lane == 0) {
-                uint64_t seen = __hip_atomic_load(&a.mirror[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                // relaxed checks (an acquire at agent scope would invalidate
+                // this CU's vector L1 on every check, under the searches of the
+                // other waves); the acquire fence follows once the item is there
+                uint64_t seen = __hip_atomic_load(&a.mirror[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (seen > t) {
                     state = 1;
-                } else if (__hip_atomic_load(&a.mirror[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+                } else if (__hip_atomic_load(&a.mirror[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     state = 2;
                 } else {
                     if (seen == t) {  // this wave is next in line: poll the host
@@ -432,12 +435,20 @@ __global__ __launch_bounds__(256) void serve_kernel(ServeArgs a)
                         }
                     }
                     if (state == 0 && ++idle > a.idle_limit) state = 2;
+                    if (state == 0 && seen == t) state = 3;
                 }
             }
             state = __shfl(state, 0, 64);
-            if (state == 1) break;
+            if (state == 1) {
+                __atomic_thread_fence(__ATOMIC_ACQUIRE);  // pairs with the publisher's release
+                break;
+            }
             if (state == 2) return;
-            __builtin_amdgcn_s_sleep(16);
+            // The poller re-reads the host soon; every other wave backs off
+            // longer, so that idle waves do not crowd the mirror's cache line
+            // while searches run.
+            if (state == 3) __builtin_amdgcn_s_sleep(16);
+            else __builtin_amdgcn_s_sleep(127);
         }
         idle = 0;
         const uint64_t slot = t % a.cap;

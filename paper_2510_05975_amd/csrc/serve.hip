@@ -156,7 +156,7 @@ cng_status cng_serve_start(const cng_serve_config *c, void *workspace, size_t ws
     a.head = (unsigned long long *)workspace;
     a.mirror = (uint64_t *)workspace + 2;
     a.max_k = (uint32_t)c->max_k;
-    a.idle_limit = 1u << 23;  // about ten seconds without work ends the grid
+    a.idle_limit = 1u << 21;  // some seconds without work end the grid
     e = cng::launch_serve(a, waves, s->stream);
     if (e != hipSuccess) {
         release_all(s);
