@@ -261,7 +261,9 @@ def main():
         cand_s = float(np.median([s["stats"]["ms_candidates"] for s in steps])) / 1e3
         flops_alg = float(n) * (n - 1) * d        # n(n-1)/2 pairs x 2d
         tflops = flops_alg / cand_s / 1e12
-        peak = BF16_MFMA_TFLOPS if st.get("filter_dtype") == 1 else FP32_MFMA_TFLOPS
+        # forms 1 (exact bf16) and 2 (bf16 hi / lo pairs, three products per
+        # algorithmic one) run on the bf16 matrix cores, form 0 on float32 ones
+        peak = BF16_MFMA_TFLOPS if st.get("filter_dtype") in (1, 2) else FP32_MFMA_TFLOPS
         out["build_secs"] = round(float(np.median(bs)), 4)
         out["build_stages_ms"] = {kk: round(st[kk], 2) for kk in
                                   ("ms_entry", "ms_candidates", "ms_prune", "ms_backward",
@@ -271,7 +273,9 @@ def main():
                                                     "filter_dtype")}
         out["roofline_build"] = {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak,
                                  "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
-                                 "kernel": "candidate stage (filter GEMM + rerank)",
+                                 "kernel": "candidate stage (filter GEMM + rerank), " +
+                                 {0: "float32", 1: "bf16 exact", 2: "bf16 hi/lo split"}[
+                                     st.get("filter_dtype", 0)],
                                  "traffic": None}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, cng.u32(g.adj), g.entry, k, L, a.cpu_seconds)

@@ -6,10 +6,12 @@
 // column tiles.  For each pair it computes F = |y|^2 - 2 x.y on the matrix
 // cores (float32 accumulate) and appends (F, id) to the row's band when F is at
 // most the row threshold.  Three forms: bf16 inputs for small-integer data
-// (exact), bf16 hi/lo pairs for other data with d <= 128 (three products per
-// k step), float32 inputs otherwise.  Whenever a band could overflow on the next tile it
-// is compacted: sorted, and cut to F <= F_C + 2E where F_C is the C-th smallest
-// F so far and E bounds |F - (D - |x|^2)| for every column of this row (the
+// (exact), bf16 hi/lo pairs for other data (three products per k step), float32
+// inputs for the rest (larger integers, extreme magnitudes).  The bf16 forms
+// keep a wave's row fragments in registers for d <= 128 (filter_bf16) and
+// stream them through k otherwise (filter_wide).  Whenever a band could
+// overflow on the next tile it is compacted: cut to F <= F_C + 2E, where F_C is
+// the C-th smallest F so far (found by a radix select) and E bounds |F - (D - |x|^2)| for every column of this row (the
 // product and norm rounding of the filter plus the rounding of D itself).  Any
 // point of the exact top C then satisfies F <= F_C + 2E, so the band always
 // contains it.  With small-integer data every quantity is an exact integer and
@@ -18,6 +20,8 @@
 // C by (D, id) is selected by a bitonic sort.
 // Stage 3: rows whose band overflowed are recomputed exhaustively.
 #include <hip/hip_runtime.h>
+
+#include <utility>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -473,6 +477,130 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Per-lane thresholds of the 32 rows of this wave that the lane's accumulator
+// elements belong to (the 32x32 MFMA output layout).
+__device__ __forceinline__ void load_thr(float (&th)[2][16], const float *thr)
+{
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            th[i][r] = thr[wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
+}
+
+// Epilogue of a column tile of NJ blocks of 32 for the wave's 64 rows: F =
+// |y|^2 - 2 x.y against the row thresholds.  One compare per element gives a
+// wave mask per (row pair, column block); appends (rare once the thresholds
+// have settled) take positions from the register counts (mypos: next free band
+// slot of row wave * 64 + lane): a popcount per row and a prefix count per lane.
+// A row's own column (self-joins) is appended like any other and dropped by the
+// compaction and the rerank.  One column block per instantiation, so that every
+// accumulator index is a constant however many blocks a tile has.
+// Thresholds come from th (registers) or, with thr_lds set, straight from LDS.
+template <int J, int NJ>
+__device__ __forceinline__ void append_block(const FilterArgs &a, const floatx16 (&acc)[2][NJ],
+                                             const float (&ny)[NJ], const float (&th)[2][16],
+                                             const float *thr_lds, int64_t col0, int trig,
+                                             uint32_t &mypos, bool &wflag)
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float F = __builtin_fmaf(-2.0f, acc[i][J][r], ny[J]);
+            const float t = thr_lds ? thr_lds[wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)]
+                                    : th[i][r];
+            const uint64_t m = __builtin_amdgcn_ballot_w64(F <= t);
+            if (__builtin_expect(m != 0, 0)) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // lanes 32h .. 32h+31 hold row ro of this wave
+                    const int ro = i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const uint64_t hm = m & (h ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull);
+                    if (hm) {
+                        // a row holds at most CB - 32 NJ entries when a tile
+                        // starts and takes at most 32 NJ in it: every slot
+                        // taken here is below CB
+                        const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)mypos, ro);
+                        const uint32_t o = base + __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(hm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+                        if ((hm >> lane) & 1ull) {
+                            a.bandF[o] = F;
+                            a.bandI[o] = (uint32_t)(col0 + J * 32 + (lane & 31));
+                        }
+                        const uint32_t nb = base + (uint32_t)__popcll(hm);
+                        wflag |= (int)(base & (uint32_t)(a.CB - 1)) + __popcll(hm) > trig;
+                        asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mypos) : "s"(nb), "i"(ro));
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int NJ, int... J>
+__device__ __forceinline__ bool append_blocks(const FilterArgs &a, const floatx16 (&acc)[2][NJ],
+                                              const float (&ny)[NJ], const float (&th)[2][16],
+                                              const float *thr_lds, int64_t col0, int trig,
+                                              uint32_t &mypos, std::integer_sequence<int, J...>)
+{
+    bool wflag = false;
+    (append_block<J, NJ>(a, acc, ny, th, thr_lds, col0, trig, mypos, wflag), ...);
+    return wflag;
+}
+
+// Returns whether a band of this wave passed the compaction trigger.
+template <int NJ>
+__device__ __forceinline__ bool append_tile(const FilterArgs &a, const floatx16 (&acc)[2][NJ],
+                                            const float (&ny)[NJ], const float (&th)[2][16],
+                                            const float *thr_lds, int64_t col0, int trig,
+                                            uint32_t &mypos)
+{
+    return append_blocks<NJ>(a, acc, ny, th, thr_lds, col0, trig, mypos,
+                             std::make_integer_sequence<int, NJ>{});
+}
+
+// After a tile (every thread of the workgroup): when a band of the workgroup
+// passed the trigger, or after the last tile, the register counts go to LDS,
+// the bands that need it are compacted, and counts and thresholds come back.
+// An overflowed row (count -1) keeps the OVERFLOWED marker and takes nothing
+// more.
+constexpr uint32_t OVERFLOWED = 0xFFFFFFFFu;
+
+template <int BN>
+__device__ __forceinline__ void settle_bands(const FilterArgs &a, bool wflag, bool last, int *flag,
+                                             int *cnt, float *thr, const float *erow, uint32_t *keys,
+                                             uint32_t *hist, uint32_t rowstart, uint32_t &mypos,
+                                             float (&th)[2][16])
+{
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int trig = a.CB - BN;
+    if (wflag && lane == 0) flag[0] = 1;
+    lds_barrier();
+    if (flag[0] || last) {
+        cnt[wave * 64 + lane] = mypos == OVERFLOWED ? -1 : (int)(mypos - rowstart);
+        __syncthreads();  // band stores and counts of every wave complete
+        for (int li = wave; li < BM2; li += 4) {
+            const int c = cnt[li];
+            const bool need = c >= 0 && (last ? c > a.C : c > trig);
+            if (need)
+                compact_band(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
+                             keys + (size_t)wave * a.CB, hist + wave * 256, last, BN);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) flag[0] = 0;
+        {
+            const int c = cnt[wave * 64 + lane];
+            mypos = c < 0 ? OVERFLOWED : rowstart + (uint32_t)c;
+        }
+        load_thr(th, thr);
+        __syncthreads();
+    }
+}
+
 // SPLIT (general float data): every value is the sum of two bf16 numbers,
 // hi = bf16(x) and lo = bf16(x - hi), and x.y is taken as hi.hi + hi.lo + lo.hi
 // on the matrix cores (the dropped parts are below 3.1 * 2^-16 |x_k||y_k| per
@@ -512,8 +640,6 @@ void filter_bf16(FilterBf16Args A)
     // 64 rows, so these live in a register, read and written per row by lane
     // index, and go through LDS (as counts) only around compactions.
     const uint32_t rowstart = (uint32_t)(blockIdx.x * BM2 + wave * 64 + lane) * (uint32_t)a.CB;
-    // an overflowed row (threshold -inf) keeps this marker until the end
-    constexpr uint32_t OVERFLOWED = 0xFFFFFFFFu;
     // compaction once a band could not take another whole tile (measured: an
     // earlier cut, at half the capacity, costs more than the appends it saves)
     const int trig = a.CB - BN2;
@@ -580,14 +706,7 @@ void filter_bf16(FilterBf16Args A)
     __syncthreads();
     // per-lane thresholds of the 32 rows this lane sees (refreshed after compactions)
     float th[2][16];
-    auto load_thr = [&]() {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                th[i][r] = thr[wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
-    };
-    load_thr();
+    load_thr(th, thr);
 
     int buf = 0;
     for (int64_t col0 = 0; col0 < a.nc; col0 += BN2) {
@@ -644,70 +763,11 @@ void filter_bf16(FilterBf16Args A)
         // matrix phase ago, and waiting for them later would also wait for the
         // band stores of the epilogue
         if (more) stash(buf ^ 1);
-        // ---- epilogue: F = |y|^2 - 2 x.y against the row thresholds.  One
-        // compare per element gives a wave mask per (row pair, column block);
-        // appends (rare once the thresholds have settled) take positions from
-        // the register counts: a popcount per row and a prefix count per lane.
-        // A row's own column (self-joins) is appended like any other and
-        // dropped by the compaction and the rerank.
-        bool wflag = false;
+        float nyv[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const float nyj = nys[buf * BN2 + j * 32 + (lane & 31)];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float F = __builtin_fmaf(-2.0f, acc[i][j][r], nyj);
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(F <= th[i][r]);
-                    if (__builtin_expect(m != 0, 0)) {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            // lanes 32h .. 32h+31 hold row ro of this wave
-                            const int ro = i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                            const uint64_t hm = m & (h ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull);
-                            if (hm) {
-                                // a row holds at most CB - BN2 entries when a tile
-                                // starts and takes at most BN2 in it: every slot
-                                // taken here is below CB
-                                const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)mypos, ro);
-                                const uint32_t o = base + __builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(hm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-                                if ((hm >> lane) & 1ull) {
-                                    a.bandF[o] = F;
-                                    a.bandI[o] = (uint32_t)(col0 + j * 32 + (lane & 31));
-                                }
-                                const uint32_t nb = base + (uint32_t)__popcll(hm);
-                                wflag |= (int)(base & (uint32_t)(a.CB - 1)) + __popcll(hm) > trig;
-                                asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mypos) : "s"(nb), "i"(ro));
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        if (wflag && lane == 0) flag[0] = 1;
-        lds_barrier();
-        const bool last = !more;
-        if (flag[0] || last) {
-            cnt[wave * 64 + lane] = mypos == OVERFLOWED ? -1 : (int)(mypos - rowstart);
-            __syncthreads();  // band stores and counts of every wave complete
-            for (int li = wave; li < BM2; li += 4) {
-                const int c = cnt[li];
-                const bool need = c >= 0 && (last ? c > a.C : c > trig);
-                if (need)
-                    compact_band(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
-                                 keys + (size_t)wave * a.CB, hist + wave * 256, last, BN2);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) flag[0] = 0;
-            {
-                const int c = cnt[wave * 64 + lane];  // -1: overflowed, takes nothing more
-                mypos = c < 0 ? OVERFLOWED : rowstart + (uint32_t)c;
-            }
-            load_thr();
-            __syncthreads();
-        }
+        for (int j = 0; j < 2; ++j) nyv[j] = nys[buf * BN2 + j * 32 + (lane & 31)];
+        const bool wflag = append_tile<2>(a, acc, nyv, th, nullptr, col0, trig, mypos);
+        settle_bands<BN2>(a, wflag, !more, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
         buf ^= 1;
     }
     for (int li = threadIdx.x; li < BM2; li += 256) {
@@ -723,6 +783,191 @@ size_t filter_bf16_lds_bytes(int K, int CB, bool split)
 {
     return (size_t)2 * (split ? 2 : 1) * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 +
            (size_t)BM2 * 4 * 3 + 16 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
+}
+
+// ---------------------------------------------------------------- wide bf16 filter
+// For d > 128 the fragments of a wave's rows over the whole k range no longer
+// fit in registers, so both operands stream through k in stages of KC values
+// (the row length K is a multiple of 2 KC).  A workgroup owns 256 rows (64 per
+// wave, as in filter_bf16) and sweeps column tiles of BNW.  Only its own wave
+// reads a row fragment, so each wave loads its rows straight from global memory
+// into registers; the column tile, read by all four waves, goes through LDS.
+// Both are double-buffered one stage ahead: stages alternate between buffer
+// pairs 0 and 1, and the prefetch issued in a tile's last stage is the next
+// tile's first.  Same forms (exact bf16, split hi / lo) and the same epilogue as
+// filter_bf16.
+template <int KC, int BNW, bool SPLIT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void filter_wide(FilterBf16Args A, int K)
+{
+    constexpr int KSS = KC / 16;            // k steps per stage
+    constexpr int NP = SPLIT ? 2 : 1;       // parts per value: hi (and lo)
+    constexpr int BSTR = KC + 8;            // LDS row of a column: 16 B pad against bank conflicts
+    constexpr int CPR = KC / 8;             // 16-byte chunks per column, part and stage
+    constexpr int PER_T = NP * BNW * CPR / 256;
+    static_assert(PER_T * 256 == NP * BNW * CPR, "whole chunks per thread");
+    constexpr int NJ = BNW / 32;
+    const FilterArgs &a = A.f;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);  // 2 x NP x BNW x BSTR
+    float *thr = reinterpret_cast<float *>(Bs + 2 * NP * BNW * BSTR);
+    float *erow = thr + BM2;
+    int *cnt = reinterpret_cast<int *>(erow + BM2);
+    int *flag = cnt + BM2;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(flag + 4);  // 4 x 256
+    uint32_t *keys = hist + 4 * 256;                          // 4 x CB
+
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM2;
+    const int64_t rend = a.r0 + a.chunk < a.nr ? a.r0 + a.chunk : a.nr;
+    for (int li = threadIdx.x; li < BM2; li += 256) {
+        int64_t gi = row0 + li;
+        bool live = gi < rend;
+        thr[li] = live ? __builtin_inff() : -__builtin_inff();
+        erow[li] = live ? a.E[gi] : 0.f;
+        cnt[li] = 0;
+    }
+    if (threadIdx.x == 0) flag[0] = 0;
+    const uint32_t rowstart = (uint32_t)(blockIdx.x * BM2 + wave * 64 + lane) * (uint32_t)a.CB;
+    const int trig = a.CB - BNW;
+    uint32_t mypos = rowstart;
+
+    // element offsets of this lane's row fragments; rows past the end read the
+    // last row (a dead row never takes a column), so every load is unconditional
+    size_t aoff[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        int64_t gi = row0 + wave * 64 + i * 32 + (lane & 31);
+        gi = gi < rend ? gi : rend - 1;
+        aoff[i] = (size_t)gi * K + (lane >> 5) * 8;
+    }
+    bf16x8 a0[2][KSS][NP], a1[2][KSS][NP];
+    auto fetch_a = [&](bf16x8 (&dst)[2][KSS][NP], int k0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int ks = 0; ks < KSS; ++ks) {
+                dst[i][ks][0] = *reinterpret_cast<const bf16x8 *>(A.rows16 + aoff[i] + k0 + ks * 16);
+                if constexpr (SPLIT)
+                    dst[i][ks][NP - 1] =
+                        *reinterpret_cast<const bf16x8 *>(A.rows16lo + aoff[i] + k0 + ks * 16);
+            }
+    };
+    // column tile stage: columns past the end read the last column (their F
+    // is NaN through the norm)
+    u32x4 pre[PER_T];
+    auto fetch_b = [&](int64_t col0, int k0) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            const int c = threadIdx.x + 256 * i;
+            const int part = c / (BNW * CPR), cc = c % (BNW * CPR);
+            const int col = cc / CPR, kc = cc % CPR;
+            int64_t gj = col0 + col;
+            gj = gj < a.nc ? gj : a.nc - 1;
+            const uint16_t *src = (SPLIT && part) ? A.cols16lo : A.cols16;
+            pre[i] = *reinterpret_cast<const u32x4 *>(src + (size_t)gj * K + k0 + kc * 8);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            const int c = threadIdx.x + 256 * i;
+            const int part = c / (BNW * CPR), cc = c % (BNW * CPR);
+            const int col = cc / CPR, kc = cc % CPR;
+            *reinterpret_cast<u32x4 *>(Bs + ((size_t)(buf * NP + part) * BNW + col) * BSTR + kc * 8) =
+                pre[i];
+        }
+    };
+    floatx16 acc[2][NJ];
+    auto stage = [&](int buf, const bf16x8 (&af)[2][KSS][NP]) {
+        const uint16_t *Bb = Bs + (size_t)buf * NP * BNW * BSTR + (lane & 31) * BSTR + (lane >> 5) * 8;
+#pragma unroll
+        for (int ks = 0; ks < KSS; ++ks) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(Bb + j * 32 * BSTR + ks * 16);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][ks][0], bh, acc[i][j], 0, 0, 0);
+                if constexpr (SPLIT) {
+                    const bf16x8 bl =
+                        *reinterpret_cast<const bf16x8 *>(Bb + (BNW + j * 32) * BSTR + ks * 16);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][ks][0], bl, acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][ks][NP - 1], bh, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    const int S = K / KC;  // even
+    fetch_a(a0, 0);
+    fetch_b(0, 0);
+    stash(0);
+    __syncthreads();
+    float th[2][16];
+    load_thr(th, thr);
+    for (int64_t col0 = 0; col0 < a.nc; col0 += BNW) {
+        const bool more_tiles = col0 + BNW < a.nc;
+        float nyv[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int64_t gj = col0 + j * 32 + (lane & 31);
+            nyv[j] = a.ny[gj < a.nc ? gj : a.nc - 1];
+            if (gj >= a.nc) nyv[j] = __builtin_nanf("");
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[i][j] = floatx16{};
+        for (int s = 0; s < S; s += 2) {
+            // stage s from buffers 0; stage s + 1 (same tile: S is even) into buffers 1
+            fetch_a(a1, (s + 1) * KC);
+            fetch_b(col0, (s + 1) * KC);
+            // keep the loads ahead of the matrix phase (the scheduler would
+            // otherwise sink them next to their first use)
+            __builtin_amdgcn_sched_barrier(0);
+            stage(0, a0);
+            stash(1);
+            lds_barrier();
+            // stage s + 1 from buffers 1; stage s + 2, or the next tile's first, into buffers 0
+            const bool in_tile = s + 2 < S;
+            const bool more = in_tile || more_tiles;
+            if (more) {
+                fetch_a(a0, in_tile ? (s + 2) * KC : 0);
+                fetch_b(in_tile ? col0 : col0 + BNW, in_tile ? (s + 2) * KC : 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            stage(1, a1);
+            if (more) stash(0);
+            lds_barrier();
+        }
+        const bool wflag = append_tile<NJ>(a, acc, nyv, th, thr, col0, trig, mypos);
+        settle_bands<BNW>(a, wflag, !more_tiles, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
+    }
+    for (int li = threadIdx.x; li < BM2; li += 256) {
+        int64_t gi = row0 + li;
+        if (gi < rend) {
+            a.cnt[gi - a.r0] = cnt[li];
+            if (cnt[li] < 0) atomicAdd(&a.st->overflow, 1u);
+        }
+    }
+}
+
+// Stage depth, tile width and occupancy of the wide filter (measured at
+// 262144 x 960: 32 / 256 / 1 wave per SIMD 0.67 s; 32 / 128 / 1 0.73 s;
+// 16 / 128 / 2 1.55 s)
+constexpr int KCW = 32;   // k values per stage
+constexpr int BNW = 256;  // columns per tile
+constexpr int WPEW = 1;   // waves per SIMD
+
+size_t filter_wide_lds_bytes(int CB, bool split)
+{
+    return (size_t)2 * (split ? 2 : 1) * BNW * (KCW + 8) * 2 + (size_t)BM2 * 4 * 3 + 16 +
+           (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
 }
 
 // ---------------------------------------------------------------- rerank
@@ -917,6 +1162,13 @@ void pick_rerank(int d, RerankFn &r, ExhFn &e)
     return pick_gr<32, 32, VEC>(r, e);
 }
 
+// Row length of the bf16 copies: whole k steps of 16 in an even count for
+// filter_bf16 (d <= 128), whole stage pairs for filter_wide.
+int bf16_row_len(int d)
+{
+    return d <= 128 ? (d + 31) / 32 * 32 : (d + 2 * KCW - 1) / (2 * KCW) * (2 * KCW);
+}
+
 size_t filter_lds_bytes(int CB)
 {
     size_t b = (size_t)BK * (BM + APAD) * 4 * 2 + (size_t)BM * 4 * 2 + (size_t)(BM + 2) * 4;
@@ -929,8 +1181,10 @@ size_t filter_lds_bytes(int CB)
 KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
 {
     KnnPlan p;
-    int CB = band > 0 ? next_pow2(band) : next_pow2(2 * C + BN);
+    int CB = band > 0 ? next_pow2(band) : next_pow2(2 * C + (d > 128 ? BNW : BN));
     if (CB < 64) CB = 64;
+    // a band takes a whole column tile of the filter before its first cut
+    if (d > 128 && CB < BNW) CB = BNW;
     p.band = CB;
     const size_t budget = (size_t)1 << 30;  // band bytes per pass
     int64_t chunk = (int64_t)(budget / ((size_t)CB * 8));
@@ -942,8 +1196,8 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
     p.chunk_rows = chunk;
     p.bytes = align256((size_t)nc * 4) + align256((size_t)nr * 4) * 2 + align256(sizeof(PrepOut)) +
               align256((size_t)chunk * CB * 4) * 2 + align256((size_t)chunk * 4);
-    if (d <= 128) {  // bf16 copies (hi and lo parts) for the matrix-core filters
-        const int K = (d + 31) / 32 * 32;
+    {  // bf16 copies (hi and lo parts) for the matrix-core filters
+        const int K = bf16_row_len(d);
         p.bytes += (align256((size_t)nc * K * 2) + align256((size_t)nr * K * 2)) * 2;
     }
     return p;
@@ -969,17 +1223,14 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     w += align256((size_t)plan.chunk_rows * CB * 4);
     int *cnt = (int *)w;
     w += align256((size_t)plan.chunk_rows * 4);
-    const int K16 = (d + 31) / 32 * 32;  // bf16 row length: whole k steps of 16, an even count
-    uint16_t *cols16 = nullptr, *rows16 = nullptr, *cols16lo = nullptr, *rows16lo = nullptr;
-    if (d <= 128) {
-        cols16 = (uint16_t *)w;
-        w += align256((size_t)nc * K16 * 2);
-        rows16 = (uint16_t *)w;
-        w += align256((size_t)nr * K16 * 2);
-        cols16lo = (uint16_t *)w;
-        w += align256((size_t)nc * K16 * 2);
-        rows16lo = (uint16_t *)w;
-    }
+    const int K16 = bf16_row_len(d);
+    uint16_t *cols16 = (uint16_t *)w;
+    w += align256((size_t)nc * K16 * 2);
+    uint16_t *rows16 = (uint16_t *)w;
+    w += align256((size_t)nr * K16 * 2);
+    uint16_t *cols16lo = (uint16_t *)w;
+    w += align256((size_t)nc * K16 * 2);
+    uint16_t *rows16lo = (uint16_t *)w;
 
     hipLaunchKernelGGL(init_prep, dim3(1), dim3(1), 0, stream, st);
     hipLaunchKernelGGL(prep_cols, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream, cols, nc,
@@ -998,9 +1249,12 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     bool exact = h.all_int != 0 &&
                  (h.any_neg ? 4.0 * d * M * M <= lim : 2.0 * d * M * M <= lim);
     // bf16 holds every integer of magnitude <= 256 exactly
-    const bool use_bf16 = exact && d <= 128 && M <= 256.0;
-    // other data with d <= 128: hi / lo bf16 parts, three products per k step
-    const bool use_split = !use_bf16 && !exact && d <= 128;
+    const bool use_bf16 = exact && M <= 256.0;
+    // other data: hi / lo bf16 parts, three products per k step.  Within this
+    // range of magnitudes no part is subnormal where it matters and no squared
+    // norm overflows; outside it the float32 filter runs.
+    const bool use_split = !use_bf16 && !exact && M >= 0x1p-60 && M <= 0x1p60;
+    const bool wide = d > 128;
     if (exact_int) *exact_int = exact ? 1 : 0;
     if (dtype) *dtype = use_bf16 ? 1 : use_split ? 2 : 0;
     const bool self = rows == cols && nr == nc;
@@ -1041,7 +1295,13 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     for (int64_t r0 = 0; r0 < nr; r0 += plan.chunk_rows) {
         const int64_t chunk = nr - r0 < plan.chunk_rows ? nr - r0 : plan.chunk_rows;
         FilterArgs fa{rows, nr, r0, chunk, cols, nc, d, C, exclude_self, ny, E, CB, bandF, bandI, cnt, st};
-        if (use_bf16 || use_split) {
+        if ((use_bf16 || use_split) && wide) {
+            FilterBf16Args fb{fa, rows16, cols16, rows16lo, cols16lo};
+            const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
+            const unsigned lds = (unsigned)filter_wide_lds_bytes(CB, use_split);
+            if (use_split) hipLaunchKernelGGL((filter_wide<KCW, BNW, true, WPEW>), dim3(blocks), dim3(256), lds, stream, fb, K16);
+            else hipLaunchKernelGGL((filter_wide<KCW, BNW, false, WPEW>), dim3(blocks), dim3(256), lds, stream, fb, K16);
+        } else if (use_bf16 || use_split) {
             FilterBf16Args fb{fa, rows16, cols16, rows16lo, cols16lo};
             const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
             const unsigned lds = (unsigned)filter_bf16_lds_bytes(K16, CB, use_split);

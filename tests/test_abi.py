@@ -36,7 +36,7 @@ def test_build_params_rejected(bad):
     assert cng.lib().cng_last_error().decode() != ""
 
 
-@pytest.mark.parametrize("bad", [dict(R=200, extra=100), dict(band=1024), dict(C=300), dict(Lc=1000),
+@pytest.mark.parametrize("bad", [dict(R=200, extra=100), dict(band=8192), dict(C=300), dict(Lc=1000),
                                  dict(alpha_step=1e-6, alpha_max=2.0)])
 def test_build_params_unsupported(bad):
     nb = C.c_size_t(0)

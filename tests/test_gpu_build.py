@@ -56,7 +56,15 @@ def test_knn_queries_vs_points_ragged():
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
 
 
-@pytest.mark.parametrize("d", [1, 3, 7, 33, 100, 129, 300])
+def test_knn_queries_vs_points_ragged_wide():
+    # d = 960: the streamed filter, 77 query rows and 1999 columns (ragged tiles)
+    x, q = workloads.generate(3, n=1999, nq=77)
+    ids, D, _ = gpu_knn(q, x, 10, False)
+    oids, oD = oracle.knn(q, x, 10)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+@pytest.mark.parametrize("d", [1, 3, 7, 33, 100, 129, 136, 200, 300])
 def test_knn_dims(d):
     x, _ = workloads.uniform_cube(700, 1, d, seed=d)
     ids, D, _ = gpu_knn(x, x, 16, True)
@@ -143,13 +151,19 @@ def test_connect_capacity_error():
 
 
 # ---------------------------------------------------------------- whole build
-@pytest.mark.parametrize("case", [(1, 10000, 24, 64), (2, 5000, 32, 128), (4, 4000, 32, 128)])
+# filter form per workload: 1 = exact bf16 (integers), 2 = bf16 hi / lo pairs
+FORM = {1: 2, 2: 1, 3: 2, 4: 2}
+
+
+@pytest.mark.parametrize("case", [(1, 10000, 24, 64), (2, 5000, 32, 128), (4, 4000, 32, 128),
+                                  (3, 1500, 48, 192)])
 def test_build_bit_exact(case):
     cfg, n, R, C = case
     print(f"build cfg{cfg} n={n}", flush=True)
     x, _ = workloads.generate(cfg, n=n, nq=1)
     oadj, oe, oadded = oracle.build(x, R, C, 1.2)
     g = cng.build(dev(x), R, C, 1.2)
+    assert g.stats["filter_dtype"] == FORM[cfg]
     assert g.entry == oe
     assert (host_ids(g.adj) == oadj).all()
     assert g.stats["connect_added"] == oadded
@@ -166,3 +180,24 @@ def test_knn_small_integer_bf16_path(d, lo, hi):
     torch.cuda.synchronize()
     oids, oD = oracle.knn(x, x, 40, exclude_self=True)
     assert (host_ids(ids) == oids).all() and same_f32(D.cpu().numpy(), f32_of(oD))
+
+
+@pytest.mark.parametrize("d,lo,hi", [(129, 0, 100), (200, -50, 51), (300, 0, 100)])
+def test_knn_small_integer_wide_path(d, lo, hi):
+    """Small-integer data with d > 128 takes the exact streamed bf16 filter."""
+    g = np.random.default_rng(7 * d + lo)
+    x = g.integers(lo, hi, size=(2100, d)).astype(np.float32)
+    r = dev(x)
+    ids, D, _ = cng.knn(r, r, 40, exclude_self=True)
+    torch.cuda.synchronize()
+    oids, oD = oracle.knn(x, x, 40, exclude_self=True)
+    assert (host_ids(ids) == oids).all() and same_f32(D.cpu().numpy(), f32_of(oD))
+
+
+def test_build_wide_integer_form():
+    g = np.random.default_rng(11)
+    x = g.integers(0, 60, size=(2500, 160)).astype(np.float32)
+    oadj, oe, _ = oracle.build(x, 16, 48, 1.2)
+    b = cng.build(dev(x), 16, 48, 1.2)
+    assert b.stats["filter_dtype"] == 1 and b.stats["exact_integer"] == 1
+    assert b.entry == oe and (host_ids(b.adj) == oadj).all()
