@@ -75,6 +75,12 @@ struct KnnPlan {
     int64_t chunk_rows;   // rows per pass
     int band;             // per-row band capacity
     size_t bytes;         // workspace bytes
+    // self-joins: cells of the locality order (0: none) and the plan of the
+    // cell assignment (a candidate search with C = 1 against the cell samples)
+    int order_K;
+    int64_t inner_chunk;
+    int inner_band;
+    size_t inner_bytes;
 };
 KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band);
 hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int d, int C,

@@ -201,3 +201,19 @@ def test_build_wide_integer_form():
     b = cng.build(dev(x), 16, 48, 1.2)
     assert b.stats["filter_dtype"] == 1 and b.stats["exact_integer"] == 1
     assert b.entry == oe and (host_ids(b.adj) == oadj).all()
+
+
+def test_knn_locality_order_overflow_and_duplicates():
+    """Self-joins of at least 2048 points (d <= 128) sweep in locality order:
+    rows sent to the exhaustive path and many exact duplicates of a row (kept,
+    while the row itself is dropped) still give the oracle's lists."""
+    x, _ = workloads.uniform_cube(9000, 1, 24, seed=5)
+    ids, D, ovf = gpu_knn(x, x, 64, True, band=64)
+    assert ovf > 0
+    oids, oD = oracle.knn(x, x, 64, exclude_self=True)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+    g = np.random.default_rng(9)
+    x = g.integers(0, 3, size=(5000, 4)).astype(np.float32)  # 81 distinct points
+    ids, D, _ = gpu_knn(x, x, 40, True)
+    oids, oD = oracle.knn(x, x, 40, exclude_self=True)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
