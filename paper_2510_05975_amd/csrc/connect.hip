@@ -374,6 +374,9 @@ hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int
     NearestFn nf = vec ? pick_nf<true>(d) : pick_nf<false>(d);
     Counters h;
     const int64_t nseg = (n + SEG - 1) / SEG;
+    // row lengths; apply_attach keeps them current (it is the only writer of
+    // adj from here on)
+    hipLaunchKernelGGL(degrees, dim3(gb), dim3(256), 0, st, adj, W, n, s.deg);
     while (reached < n) {
         ++*rounds;
         hipLaunchKernelGGL(round_init, dim3(gb), dim3(256), 0, st, s.c, s.indeg, n);
@@ -393,7 +396,6 @@ hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int
             h.nA = 1;
         }
         const uint32_t nA = h.nA;
-        hipLaunchKernelGGL(degrees, dim3(gb), dim3(256), 0, st, adj, W, n, s.deg);
         for (int64_t off = 0; off < nA; off += BATCH) {
             const int64_t cnt = nA - off < BATCH ? nA - off : BATCH;
             SearchArgs sa{};
