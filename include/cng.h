@@ -61,7 +61,7 @@ typedef struct {
     double tau;          /* tau of Eq. (1), >= 0 */
     uint32_t flags;      /* CNG_BUILD_* */
     int32_t Lc;          /* beam width of the connectivity searches (0 = C) */
-    int32_t band;        /* per-row capacity of the candidate filter, <= 4096, rounded up to a
+    int32_t band;        /* per-row capacity of the candidate filter, <= 2048, rounded up to a
                             power of two (0 = automatic) */
     int32_t visited_log2;/* log2 of the search visited-table slots (0 = automatic) */
     double alpha_max;    /* adaptive alpha (Algorithm 4): largest alpha tried, >= alpha */

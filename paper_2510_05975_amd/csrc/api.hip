@@ -98,7 +98,7 @@ cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSiz
     s = check_adaptive(p->alpha, p->alpha_max, p->alpha_step);
     if (s != CNG_OK) return s;
     if (p->Lc < 0) return fail(CNG_EINVAL, "Lc=%d must be >= 0", p->Lc);
-    if (p->band < 0 || p->band > 4096) return fail(CNG_EUNSUPPORTED, "band=%d must be in [0, 4096]", p->band);
+    if (p->band < 0 || p->band > 2048) return fail(CNG_EUNSUPPORTED, "band=%d must be in [0, 2048]", p->band);
     if (p->visited_log2 != 0 && (p->visited_log2 < 6 || p->visited_log2 > 14))
         return fail(CNG_EINVAL, "visited_log2=%d must be 0 or in [6, 14]", p->visited_log2);
     z->Ceff = (int64_t)p->C > n - 1 ? (int)(n - 1) : p->C;
@@ -246,7 +246,7 @@ cng_status cng_knn_workspace_size(int64_t nr, int64_t nc, int32_t d, int32_t C, 
     if (nr < 0 || nr > MAX_N || nc < 1 || nc > MAX_N) return fail(CNG_EINVAL, "nr/nc out of range");
     if (d < 1 || d > 4096) return fail(CNG_EINVAL, "d out of range");
     if (C < 1) return fail(CNG_EINVAL, "C must be >= 1");
-    if (band < 0 || band > 4096) return fail(CNG_EUNSUPPORTED, "band must be in [0, 4096]");
+    if (band < 0 || band > 2048) return fail(CNG_EUNSUPPORTED, "band must be in [0, 2048]");
     int Ce = C;
     if (band == 0 && 2 * Ce + 128 > 512) return fail(CNG_EUNSUPPORTED, "C=%d exceeds 192", C);
     *bytes = cng::knn_plan(nr, nc, d, Ce, band).bytes;

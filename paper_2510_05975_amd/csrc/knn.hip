@@ -10,9 +10,10 @@
 // inputs for the rest (larger integers, extreme magnitudes).  The bf16 forms
 // keep a wave's row fragments in registers for d <= 128 (filter_bf16) and
 // stream them through k otherwise (filter_wide).  Whenever a band could
-// overflow on the next tile it is compacted: cut to F <= F_C + 2E, where F_C is
-// the C-th smallest F so far (found by a radix select) and E bounds |F - (D - |x|^2)| for every column of this row (the
-// product and norm rounding of the filter plus the rounding of D itself).  Any
+// overflow on the next tile it is compacted: cut to F <= F_C + 2E, where F_C
+// is the C-th smallest F so far and E bounds |F - (D - |x|^2)| for every
+// column of this row (the product and norm rounding of the filter plus the
+// rounding of D itself).  Any
 // point of the exact top C then satisfies F <= F_C + 2E, so the band always
 // contains it.  With small-integer data every quantity is an exact integer and
 // E = 0.
@@ -172,7 +173,7 @@ __device__ __forceinline__ int64_t first_tile(const FilterArgs &a, int64_t row0,
 struct FilterLds {
     float *As, *Bs, *thr, *erow;
     int *cnt;
-    uint64_t *sort;  // 4 x CB
+    uint64_t *sort;  // 4 x CB: per wave the keys, then the ids, of a band
     uint32_t *hist;  // 4 x 256
 };
 
@@ -183,12 +184,15 @@ struct FilterLds {
 // of `bn` columns is marked overflowed (cnt = -1, threshold -inf): that row is
 // recomputed exhaustively.  After the last tile a band may stay large (no
 // further appends follow).
+// `keys` is the wave's LDS scratch of 2 CB words: the order-preserving keys,
+// then the ids of the band, staged once so that the later passes read LDS only.
 __device__ void compact_band(const FilterArgs &a, int64_t lr, float *thr_slot, int *cnt_slot,
                              float erow, uint32_t *keys, uint32_t *hist, bool last, int bn)
 {
     const int lane = lane_id();
     float *bF = a.bandF + (size_t)lr * a.CB;
     uint32_t *bI = a.bandI + (size_t)lr * a.CB;
+    uint32_t *ids = keys + a.CB;
     int c = *cnt_slot;
     if (c > a.CB) c = a.CB;
     int keep = c;
@@ -197,22 +201,36 @@ __device__ void compact_band(const FilterArgs &a, int64_t lr, float *thr_slot, i
     // the key ~0u: above every threshold, so it is never kept
     const uint32_t self = a.exclude_self ? (uint32_t)(a.r0 + lr) : NONE;
     int real = 0;
-    for (int e0 = 0; e0 < c; e0 += 64) {
-        const int e = e0 + lane;
-        bool ok = false;
-        if (e < c) {
-            ok = bI[e] != self;
-            keys[e] = ok ? fkey(bF[e]) : ~0u;
+    // stage the band: the loads of 8 entries per lane are all issued before
+    // the first is used (one memory round trip per 512 entries, not per 64)
+    for (int e0 = 0; e0 < c; e0 += 8 * 64) {
+        uint32_t ib[8];
+        float fb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 64 + lane;
+            ib[u] = e < c ? bI[e] : NONE;
+            fb[u] = e < c ? bF[e] : 0.f;
         }
-        real += __popcll(ballot(ok));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 64 + lane;
+            const bool ok = e < c && ib[u] != self;
+            if (e < c) {
+                keys[e] = ok ? fkey(fb[u]) : ~0u;
+                ids[e] = ib[u];
+            }
+            real += __popcll(ballot(ok));
+        }
     }
+    wave_sync();
     if (real < c && real < a.C) {
         // too few to cut: drop the row's own column only
         int out = 0;
         for (int e0 = 0; e0 < c; e0 += 64) {
             const int e = e0 + lane;
             const bool in = e < c && keys[e] != ~0u;
-            const uint32_t id = in ? bI[e] : 0u;
+            const uint32_t id = in ? ids[e] : 0u;
             const uint64_t bm = ballot(in);
             const int p = out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
@@ -274,7 +292,7 @@ __device__ void compact_band(const FilterArgs &a, int64_t lr, float *thr_slot, i
         for (int e0 = 0; e0 < c; e0 += 64) {
             const int e = e0 + lane;
             const bool in = e < c && keys[e] <= tk;
-            const uint32_t id = in ? bI[e] : 0u;
+            const uint32_t id = in ? ids[e] : 0u;
             const uint64_t bm = ballot(in);
             const int p = out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
@@ -607,7 +625,7 @@ __device__ __forceinline__ void settle_bands(const FilterArgs &a, bool wflag, bo
             const bool need = c >= 0 && (last ? c > a.C : c > trig);
             if (need)
                 compact_band(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
-                             keys + (size_t)wave * a.CB, hist + wave * 256, last, BN);
+                             keys + (size_t)wave * 2 * a.CB, hist + wave * 256, last, BN);
         }
         __syncthreads();
         if (threadIdx.x == 0) flag[0] = 0;
@@ -640,7 +658,7 @@ void filter_bf16(FilterBf16Args A)
     int *cnt = reinterpret_cast<int *>(erow + BM2);                // band counts, during compaction
     int *flag = cnt + BM2;                                          // [0]: a band needs compaction
     uint32_t *hist = reinterpret_cast<uint32_t *>(flag + 4);        // 4 x 256
-    uint32_t *keys = hist + 4 * 256;                                // 4 x CB
+    uint32_t *keys = hist + 4 * 256;                                // 4 x 2 CB
 
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM2;
@@ -805,7 +823,7 @@ void filter_bf16(FilterBf16Args A)
 size_t filter_bf16_lds_bytes(int K, int CB, bool split)
 {
     return (size_t)2 * (split ? 2 : 1) * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 +
-           (size_t)BM2 * 4 * 3 + 16 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
+           (size_t)BM2 * 4 * 3 + 16 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 8;
 }
 
 // ---------------------------------------------------------------- wide bf16 filter
@@ -838,7 +856,7 @@ void filter_wide(FilterBf16Args A, int K)
     int *cnt = reinterpret_cast<int *>(erow + BM2);
     int *flag = cnt + BM2;
     uint32_t *hist = reinterpret_cast<uint32_t *>(flag + 4);  // 4 x 256
-    uint32_t *keys = hist + 4 * 256;                          // 4 x CB
+    uint32_t *keys = hist + 4 * 256;                          // 4 x 2 CB
 
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM2;
@@ -994,7 +1012,7 @@ constexpr int WPEW = 1;   // waves per SIMD
 size_t filter_wide_lds_bytes(int CB, bool split)
 {
     return (size_t)2 * (split ? 2 : 1) * BNW * (KCW + 8) * 2 + (size_t)BM2 * 4 * 3 + 16 +
-           (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
+           (size_t)4 * 256 * 4 + (size_t)4 * CB * 8;
 }
 
 // ---------------------------------------------------------------- rerank
