@@ -60,13 +60,11 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g)
     const bool iok = ia < g.M, jok = jb < g.N;
     if (BF16) {
         // rows of A contiguous (forward products): two 16-byte loads per lane
-        // and k step; the k loop is unrolled so that the loads of several
-        // steps are in flight together
+        // and k step
         const bool avec = g.rk == nullptr && g.as1 == 1 && (g.K & 15) == 0 && (g.as0 & 3) == 0 &&
                           ((uintptr_t)g.A & 15) == 0;
         if (avec) {
             const float *arow = g.A + (iok ? (g.ri ? (int64_t)g.ri[ia] : ia) * g.as0 : 0);
-#pragma unroll 4
             for (int k0 = 0; k0 < g.K; k0 += 16) {
                 const int kb = k0 + (lane >> 5) * 8;
                 float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;

@@ -157,9 +157,8 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int qcap, int vlog2)
 template <int G, int RND, bool VEC, int QS, int UB, int ST>
 __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
 {
-    constexpr int NG = 64 / G;
     const int lane = lane_id();
-    const int grp = lane / G, gl = lane % G;
+    const int gl = lane % G;
     const int d = a.d;
     const int Leff = a.Leff;
 
