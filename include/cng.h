@@ -186,8 +186,10 @@ cng_status cng_connect(const float *points, int64_t n, int32_t d, uint32_t *adj,
  *   hops [nq], ndc [nq]: optional (NULL allowed): explored points and
  *   distance evaluations per query.
  *   visited_log2: log2 of the per-query visited-table slots in LDS, 6..14
- *   (0 = automatic).  The table may forget old entries when full; results do
- *   not depend on it, only ndc does.
+ *   (0 = automatic: the largest of 2^11 .. 2^13 slots with which every query
+ *   of the launch can be resident on the GPU at once, else 2^10).  The table
+ *   may forget old entries when full; results do not depend on it, only ndc
+ *   and speed do.
  * Requires W <= 256 and d <= 4096. */
 cng_status cng_search(const float *points, int64_t n, int32_t d, const uint32_t *adj, int32_t W,
                       const float *queries, int64_t nq, int32_t k, int32_t L,

@@ -199,7 +199,7 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
     int64_t rounds = 0, added = 0;
     if (p->flags & CNG_BUILD_CONNECT) {
         int cap = 0;
-        const int vl = p->visited_log2 ? p->visited_log2 : cng::search_default_vlog2(z.Lc);
+        const int vl = p->visited_log2;  // 0: chosen per round by the batch size
         e = cng::run_connect(points, n, d, adj, z.W, entry_h, z.Lc, vl, scratch, st, &rounds, &added, &cap);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "connect");
@@ -371,7 +371,7 @@ cng_status cng_connect(const float *points, int64_t n, int32_t d, uint32_t *adj,
     hipStream_t st = (hipStream_t)stream;
     int64_t rounds = 0, added = 0;
     int cap = 0;
-    const int vl = visited_log2 ? visited_log2 : cng::search_default_vlog2(Lc);
+    const int vl = visited_log2;  // 0: chosen per round by the batch size
     hipError_t e = cng::run_connect(points, n, d, adj, W, entry, Lc, vl, workspace, st, &rounds, &added, &cap);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "connect");
@@ -424,7 +424,7 @@ static cng_status search_impl(const float *points, const void *vecs, int32_t dty
     a.dists = dists;
     a.hops = hops;
     a.ndc = ndc;
-    a.vlog2 = visited_log2 ? visited_log2 : cng::search_default_vlog2(Leff);
+    a.vlog2 = visited_log2 ? visited_log2 : cng::search_default_vlog2(Leff, nq);
     hipError_t e = cng::launch_search(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "search");
     return ok();
@@ -626,7 +626,7 @@ cng_status cng_entry_labels(const float *points, int64_t n, int32_t d, const uin
     a.n = n; a.d = d; a.adj = adj; a.W = W; a.queries = queries; a.query_ids = nullptr; a.nq = nq;
     a.k = 1; a.Leff = L; a.entries = nav_dev; a.per_query_entry = 0;
     a.ids = top; a.dists = topd; a.hops = nullptr; a.ndc = nullptr;
-    a.vlog2 = cng::search_default_vlog2(L);
+    a.vlog2 = cng::search_default_vlog2(L, nq);
     e = cng::launch_search(a, st);
     // 2. label = entry node nearest to that point, by (D, index)
     if (e == hipSuccess) e = cng::gather_points(points, d, top, nq, found, st);

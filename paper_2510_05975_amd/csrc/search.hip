@@ -505,15 +505,30 @@ ServeFn pick_serve(int d)
 
 // Measured on 1M x 128 (beam 48..128): a 1024-slot table beats larger ones,
 // whose LDS cost in occupancy outweighs the distance evaluations they save.
-int search_default_vlog2(int Leff)
-{
-    return Leff <= 128 ? 10 : Leff <= 256 ? 11 : 12;
-}
-
 size_t search_lds_per_wave(int Leff, int vlog2)
 {
     int qs = Leff <= 64 ? 1 : Leff <= 128 ? 2 : Leff <= 256 ? 4 : 8;
     return wave_lds_bytes(64 * qs, vlog2);
+}
+
+// Visited-table slots (log2) of a launch of nq queries when the caller leaves
+// them open.  With more queries than the GPU holds at once, 1024 slots: the
+// smallest LDS share keeps the most waves resident (measured, 1M x 128 and
+// 10M x 128 with 10k queries: 3 % to 74 % faster than 2048 or 4096 slots for
+// L = 144 .. 512).  When every query's wave fits at once, the largest table
+// up to 8192 slots that still lets them all be resident: fewer forgotten
+// vectors to read again (1M x 960, 1000 queries, L = 352: 8192 slots 9 %
+// faster than 4096).
+int search_default_vlog2(int Leff, int64_t nq)
+{
+    const size_t lds_cu = 160 * 1024;
+    for (int vl = 13; vl > 10; --vl) {
+        const size_t wg = 4 * search_lds_per_wave(Leff, vl);  // 4 waves per workgroup
+        int64_t waves = wg > lds_cu ? 0 : 4 * (int64_t)(lds_cu / wg);
+        if (waves > 32) waves = 32;
+        if (256 * waves >= nq) return vl;
+    }
+    return 10;
 }
 
 hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
