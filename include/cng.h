@@ -325,7 +325,8 @@ typedef struct {
     int32_t waves;          /* persistent wavefronts (0: 4 per compute unit) */
     int32_t capacity;       /* ring slots = most queries in flight (0: 4 x waves) */
     int32_t max_k;          /* largest k of any request, <= 256 */
-    int32_t visited_log2;   /* 0 = 11 */
+    int32_t visited_log2;   /* 6..13; 0: the largest of 2^10 .. 2^13 slots whose
+                               workgroups of 4 waves fit the LDS of a compute unit */
 } cng_serve_config;
 
 /* Device workspace (bytes) the server keeps for its lifetime. */

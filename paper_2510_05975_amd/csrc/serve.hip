@@ -99,8 +99,8 @@ cng_status cng_serve_start(const cng_serve_config *c, void *workspace, size_t ws
     if (c->W < 1 || c->W > 256) return err(CNG_EUNSUPPORTED, "W out of range");
     if ((int64_t)c->entry >= c->n) return err(CNG_EINVAL, "entry >= n");
     if (c->max_k < 1 || c->max_k > 256) return err(CNG_EUNSUPPORTED, "max_k must be in [1, 256]");
-    if (c->visited_log2 != 0 && (c->visited_log2 < 6 || c->visited_log2 > 12))
-        return err(CNG_EINVAL, "visited_log2 must be 0 or in [6, 12]");
+    if (c->visited_log2 != 0 && (c->visited_log2 < 6 || c->visited_log2 > 13))
+        return err(CNG_EINVAL, "visited_log2 must be 0 or in [6, 13]");
     if (!workspace || ws_bytes < cng_serve_workspace_size()) return err(CNG_ENOMEM, "workspace too small");
     const size_t va = c->dtype == 1 ? 8 : c->dtype == 2 ? 4 : 16;
     if ((uintptr_t)c->points % 16 || (uintptr_t)c->vecs % va) return err(CNG_EINVAL, "vectors must be aligned");
@@ -145,7 +145,17 @@ cng_status cng_serve_start(const cng_serve_config *c, void *workspace, size_t ws
     a.base.d = c->d;
     a.base.adj = c->adj;
     a.base.W = c->W;
-    a.base.vlog2 = c->visited_log2 ? c->visited_log2 : 11;
+    if (c->visited_log2) {
+        a.base.vlog2 = c->visited_log2;
+    } else {
+        // the persistent grid keeps its waves resident anyway: the largest
+        // table (up to 8192 slots) whose workgroups still fit the LDS of a
+        // compute unit, so that fewer forgotten vectors are read again
+        const int64_t wg_per_cu = ((int64_t)waves + 4 * cus - 1) / (4 * cus);
+        int vl = 13;
+        while (vl > 10 && (size_t)wg_per_cu * 4 * cng::serve_lds_per_wave(c->d, vl) > 160 * 1024) --vl;
+        a.base.vlog2 = vl;
+    }
     a.ring = dring;
     a.items = ditems;
     a.cap = (uint64_t)cap;
