@@ -331,10 +331,10 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a)
 
 using KernelFn = void (*)(SearchArgs);
 
-template <int G, int RND, bool VEC, int ST>
+template <int G, int RND, bool VEC, int ST, int UBX = 0>
 KernelFn pick_qs(int qs)
 {
-    constexpr int UB = G == 32 ? (RND >= 16 ? 1 : 16 / RND) : G / 2;
+    constexpr int UB = UBX ? UBX : G == 32 ? (RND >= 16 ? 1 : 16 / RND) : G / 2;
     switch (qs) {
     case 1: return search_kernel<G, RND, VEC, 1, UB, ST>;
     case 2: return search_kernel<G, RND, VEC, 2, UB, ST>;
@@ -343,14 +343,21 @@ KernelFn pick_qs(int qs)
     }
 }
 
+// deep: a launch of few queries leaves the GPU mostly idle, so float32
+// searches with 257 <= d <= 1024 take twice the vectors per load batch (more
+// registers, half the memory round trips per hop).
 template <bool VEC, int ST>
-KernelFn pick_kernel(int d, int qs)
+KernelFn pick_kernel(int d, int qs, bool deep)
 {
     if (d <= 32) return pick_qs<8, 1, VEC, ST>(qs);
     if (d <= 64) return pick_qs<16, 1, VEC, ST>(qs);
     int rnd = (d + 127) / 128;
     if (rnd <= 1) return pick_qs<32, 1, VEC, ST>(qs);
     if (rnd <= 2) return pick_qs<32, 2, VEC, ST>(qs);
+    if constexpr (ST == 0) {
+        if (deep && rnd > 2 && rnd <= 4) return pick_qs<32, 4, VEC, ST, 8>(qs);
+        if (deep && rnd > 4 && rnd <= 8) return pick_qs<32, 8, VEC, ST, 4>(qs);
+    }
     if (rnd <= 4) return pick_qs<32, 4, VEC, ST>(qs);
     if (rnd <= 8) return pick_qs<32, 8, VEC, ST>(qs);
     if (rnd <= 16) return pick_qs<32, 16, VEC, ST>(qs);
@@ -358,10 +365,10 @@ KernelFn pick_kernel(int d, int qs)
 }
 
 template <bool VEC>
-KernelFn pick_store(int d, int qs, int st)
+KernelFn pick_store(int d, int qs, int st, bool deep)
 {
-    return st == 1 ? pick_kernel<VEC, 1>(d, qs) : st == 2 ? pick_kernel<VEC, 2>(d, qs)
-                                                           : pick_kernel<VEC, 0>(d, qs);
+    return st == 1 ? pick_kernel<VEC, 1>(d, qs, deep) : st == 2 ? pick_kernel<VEC, 2>(d, qs, deep)
+                                                                 : pick_kernel<VEC, 0>(d, qs, deep);
 }
 
 
@@ -541,7 +548,8 @@ hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
     const bool vec = (a.d % 4 == 0) && ((uintptr_t)a.points % 16 == 0) &&
                      ((uintptr_t)a.vecs % vbytes == 0) &&
                      (a.query_ids || (uintptr_t)a.queries % 16 == 0);
-    KernelFn fn = vec ? pick_store<true>(a.d, qs, a.store) : pick_store<false>(a.d, qs, a.store);
+    const bool deep = a.nq <= 1024;
+    KernelFn fn = vec ? pick_store<true>(a.d, qs, a.store, deep) : pick_store<false>(a.d, qs, a.store, deep);
     // the visited table may be shrunk to keep a wave within 64 KB of LDS
     // (it only changes how often a distance is recomputed, never the results)
     SearchArgs b = a;

@@ -89,6 +89,18 @@ def test_dimensions(d):
     assert_same(gpu_search(x, adj, q, 10, 24, e), oracle.search(x, adj, q, 10, 24, e))
 
 
+@pytest.mark.parametrize("d", [300, 960])
+def test_batch_size_forms(d):
+    """Launches of at most 1024 queries load twice the vectors per batch for
+    257 <= d <= 1024; both forms match the oracle."""
+    x, q = workloads.uniform_cube(1200, 1100, d, seed=d + 1)
+    adj, e, _ = oracle.build(x, 10, 20, 1.2)
+    o = oracle.search(x, adj, q, 10, 24, e)
+    assert_same(gpu_search(x, adj, q, 10, 24, e), o)  # 1100 queries
+    small = gpu_search(x, adj, q[:100], 10, 24, e)
+    assert_same(small, tuple(a[:100] for a in o))
+
+
 def test_unreachable_padding_and_invalid_ids():
     x, q = workloads.uniform_cube(50, 5, 3, seed=1)
     adj = np.full((50, 3), oracle.NONE, np.uint32)
