@@ -1329,7 +1329,9 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
     // a band takes a whole column tile of the filter before its first cut
     if (d > 128 && CB < BNW) CB = BNW;
     p.band = CB;
-    const size_t budget = (size_t)1 << 30;  // band bytes per pass
+    // band bytes per pass (measured: 1M x 128 in one pass of 4 GiB 6 % faster
+    // than four of 1 GiB; 1M x 960 in one pass of 8 GiB 3 % slower than eight)
+    const size_t budget = (size_t)(d <= 128 ? 4 : 1) << 30;
     int64_t chunk = (int64_t)(budget / ((size_t)CB * 8));
     chunk = chunk / BM * BM;
     if (chunk < BM) chunk = BM;
