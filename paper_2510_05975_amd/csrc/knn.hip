@@ -184,15 +184,20 @@ struct FilterLds {
 // of `bn` columns is marked overflowed (cnt = -1, threshold -inf): that row is
 // recomputed exhaustively.  After the last tile a band may stay large (no
 // further appends follow).
-// `keys` is the wave's LDS scratch of 2 CB words: the order-preserving keys,
-// then the ids of the band, staged once so that the later passes read LDS only.
+// `keys` is the wave's LDS scratch: CB words of order-preserving keys and,
+// with STAGE, CB more words with the ids of the band.  STAGE issues the loads
+// of 8 entries per lane before the first is used and reads only LDS after
+// that (measured: 262144 x 960 candidate search 0.665 -> 0.637 s), without it
+// the entries are read in steps of 64 and the ids again when kept (10M x 128:
+// 26.8 s against 30.9 s staged).
+template <bool STAGE>
 __device__ void compact_band(const FilterArgs &a, int64_t lr, float *thr_slot, int *cnt_slot,
                              float erow, uint32_t *keys, uint32_t *hist, bool last, int bn)
 {
     const int lane = lane_id();
     float *bF = a.bandF + (size_t)lr * a.CB;
     uint32_t *bI = a.bandI + (size_t)lr * a.CB;
-    uint32_t *ids = keys + a.CB;
+    uint32_t *ids = STAGE ? keys + a.CB : bI;
     int c = *cnt_slot;
     if (c > a.CB) c = a.CB;
     int keep = c;
@@ -201,29 +206,39 @@ __device__ void compact_band(const FilterArgs &a, int64_t lr, float *thr_slot, i
     // the key ~0u: above every threshold, so it is never kept
     const uint32_t self = a.exclude_self ? (uint32_t)(a.r0 + lr) : NONE;
     int real = 0;
-    // stage the band: the loads of 8 entries per lane are all issued before
-    // the first is used (one memory round trip per 512 entries, not per 64)
-    for (int e0 = 0; e0 < c; e0 += 8 * 64) {
-        uint32_t ib[8];
-        float fb[8];
+    if constexpr (STAGE) {
+        for (int e0 = 0; e0 < c; e0 += 8 * 64) {
+            uint32_t ib[8];
+            float fb[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * 64 + lane;
-            ib[u] = e < c ? bI[e] : NONE;
-            fb[u] = e < c ? bF[e] : 0.f;
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + lane;
+                ib[u] = e < c ? bI[e] : NONE;
+                fb[u] = e < c ? bF[e] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + lane;
+                const bool ok = e < c && ib[u] != self;
+                if (e < c) {
+                    keys[e] = ok ? fkey(fb[u]) : ~0u;
+                    ids[e] = ib[u];
+                }
+                real += __popcll(ballot(ok));
+            }
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * 64 + lane;
-            const bool ok = e < c && ib[u] != self;
+        wave_sync();
+    } else {
+        for (int e0 = 0; e0 < c; e0 += 64) {
+            const int e = e0 + lane;
+            bool ok = false;
             if (e < c) {
-                keys[e] = ok ? fkey(fb[u]) : ~0u;
-                ids[e] = ib[u];
+                ok = bI[e] != self;
+                keys[e] = ok ? fkey(bF[e]) : ~0u;
             }
             real += __popcll(ballot(ok));
         }
     }
-    wave_sync();
     if (real < c && real < a.C) {
         // too few to cut: drop the row's own column only
         int out = 0;
@@ -434,7 +449,7 @@ __global__ __launch_bounds__(NT) void filter_f32(FilterArgs a)
             const int c = s.cnt[li];
             const bool need = c >= 0 && (last ? c > a.C : c > a.CB - BN);
             if (need)
-                compact_band(a, (int64_t)blockIdx.x * BM + li, &s.thr[li], &s.cnt[li], s.erow[li],
+                compact_band<false>(a, (int64_t)blockIdx.x * BM + li, &s.thr[li], &s.cnt[li], s.erow[li],
                              reinterpret_cast<uint32_t *>(s.sort + (size_t)wave * a.CB),
                              s.hist + wave * 256, last, BN);
         }
@@ -607,7 +622,7 @@ __device__ __forceinline__ bool append_tile(const FilterArgs &a, const floatx16 
 // more.
 constexpr uint32_t OVERFLOWED = 0xFFFFFFFFu;
 
-template <int BN>
+template <int BN, bool STAGE>
 __device__ __forceinline__ void settle_bands(const FilterArgs &a, bool wflag, bool last, int *flag,
                                              int *cnt, float *thr, const float *erow, uint32_t *keys,
                                              uint32_t *hist, uint32_t rowstart, uint32_t &mypos,
@@ -624,8 +639,9 @@ __device__ __forceinline__ void settle_bands(const FilterArgs &a, bool wflag, bo
             const int c = cnt[li];
             const bool need = c >= 0 && (last ? c > a.C : c > trig);
             if (need)
-                compact_band(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
-                             keys + (size_t)wave * 2 * a.CB, hist + wave * 256, last, BN);
+                compact_band<STAGE>(a, (int64_t)blockIdx.x * BM2 + li, &thr[li], &cnt[li], erow[li],
+                                    keys + (size_t)wave * (STAGE ? 2 : 1) * a.CB, hist + wave * 256,
+                                    last, BN);
         }
         __syncthreads();
         if (threadIdx.x == 0) flag[0] = 0;
@@ -658,7 +674,7 @@ void filter_bf16(FilterBf16Args A)
     int *cnt = reinterpret_cast<int *>(erow + BM2);                // band counts, during compaction
     int *flag = cnt + BM2;                                          // [0]: a band needs compaction
     uint32_t *hist = reinterpret_cast<uint32_t *>(flag + 4);        // 4 x 256
-    uint32_t *keys = hist + 4 * 256;                                // 4 x 2 CB
+    uint32_t *keys = hist + 4 * 256;                                // 4 x CB
 
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM2;
@@ -807,7 +823,7 @@ void filter_bf16(FilterBf16Args A)
 #pragma unroll
         for (int j = 0; j < 2; ++j) nyv[j] = nys[buf * BN2 + j * 32 + (lane & 31)];
         const bool wflag = append_tile<2>(a, acc, nyv, th, nullptr, col0, trig, mypos);
-        settle_bands<BN2>(a, wflag, !more, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
+        settle_bands<BN2, false>(a, wflag, !more, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
         buf ^= 1;
         col0 = next0;
     }
@@ -823,7 +839,7 @@ void filter_bf16(FilterBf16Args A)
 size_t filter_bf16_lds_bytes(int K, int CB, bool split)
 {
     return (size_t)2 * (split ? 2 : 1) * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 +
-           (size_t)BM2 * 4 * 3 + 16 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 8;
+           (size_t)BM2 * 4 * 3 + 16 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
 }
 
 // ---------------------------------------------------------------- wide bf16 filter
@@ -990,7 +1006,7 @@ void filter_wide(FilterBf16Args A, int K)
             lds_barrier();
         }
         const bool wflag = append_tile<NJ>(a, acc, nyv, th, thr, col0, trig, mypos);
-        settle_bands<BNW>(a, wflag, !more_tiles, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
+        settle_bands<BNW, true>(a, wflag, !more_tiles, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
         col0 = next0;
     }
     for (int li = threadIdx.x; li < BM2; li += 256) {
@@ -1329,9 +1345,13 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
     // a band takes a whole column tile of the filter before its first cut
     if (d > 128 && CB < BNW) CB = BNW;
     p.band = CB;
-    // band bytes per pass (measured: 1M x 128 in one pass of 4 GiB 6 % faster
-    // than four of 1 GiB; 1M x 960 in one pass of 8 GiB 3 % slower than eight)
-    const size_t budget = (size_t)(d <= 128 ? 4 : 1) << 30;
+    // band bytes per pass: one pass when the whole band fits in 4 GiB, passes
+    // of 1 GiB otherwise (measured: 1M x 128 in one pass of 4 GiB 6 % faster
+    // than four of 1 GiB; 10M x 128 in ten passes of 4 GiB 2 % slower than
+    // 39 of 1 GiB; 1M x 960 in one pass of 8 GiB 3 % slower than eight)
+    const int64_t rows_pad = (nr + BM2 - 1) / BM2 * BM2;
+    const size_t budget = (size_t)rows_pad * CB * 8 <= ((size_t)4 << 30) ? (size_t)4 << 30
+                                                                          : (size_t)1 << 30;
     int64_t chunk = (int64_t)(budget / ((size_t)CB * 8));
     chunk = chunk / BM * BM;
     if (chunk < BM) chunk = BM;
