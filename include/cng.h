@@ -187,8 +187,8 @@ cng_status cng_connect(const float *points, int64_t n, int32_t d, uint32_t *adj,
  *   distance evaluations per query.
  *   visited_log2: log2 of the per-query visited-table slots in LDS, 6..14
  *   (0 = automatic: the largest of 2^11 .. 2^13 slots with which every query
- *   of the launch can be resident on the GPU at once, else 2^11 up to
- *   L = 128 and 2^10 beyond).  The table
+ *   of the launch can be resident on the GPU at once, else 2^10, or 2^11 for
+ *   float32 vectors up to L = 128).  The table
  *   may forget old entries when full; results do not depend on it, only ndc
  *   and speed do.
  * Requires W <= 256 and d <= 4096. */

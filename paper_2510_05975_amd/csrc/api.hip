@@ -424,7 +424,7 @@ static cng_status search_impl(const float *points, const void *vecs, int32_t dty
     a.dists = dists;
     a.hops = hops;
     a.ndc = ndc;
-    a.vlog2 = visited_log2 ? visited_log2 : cng::search_default_vlog2(Leff, nq);
+    a.vlog2 = visited_log2 ? visited_log2 : cng::search_default_vlog2(Leff, nq, a.store);
     hipError_t e = cng::launch_search(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "search");
     return ok();
@@ -626,7 +626,7 @@ cng_status cng_entry_labels(const float *points, int64_t n, int32_t d, const uin
     a.n = n; a.d = d; a.adj = adj; a.W = W; a.queries = queries; a.query_ids = nullptr; a.nq = nq;
     a.k = 1; a.Leff = L; a.entries = nav_dev; a.per_query_entry = 0;
     a.ids = top; a.dists = topd; a.hops = nullptr; a.ndc = nullptr;
-    a.vlog2 = cng::search_default_vlog2(L, nq);
+    a.vlog2 = cng::search_default_vlog2(L, nq, 0);
     e = cng::launch_search(a, st);
     // 2. label = entry node nearest to that point, by (D, index)
     if (e == hipSuccess) e = cng::gather_points(points, d, top, nq, found, st);

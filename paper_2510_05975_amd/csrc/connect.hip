@@ -418,7 +418,7 @@ hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int
             sa.dists = s.beamD;
             sa.hops = nullptr;
             sa.ndc = nullptr;
-            sa.vlog2 = vlog2 ? vlog2 : search_default_vlog2(Lc, cnt);
+            sa.vlog2 = vlog2 ? vlog2 : search_default_vlog2(Lc, cnt, 0);
             e = launch_search(sa, st);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(pick_targets, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,

@@ -57,7 +57,7 @@ struct ServeArgs {
 };
 hipError_t launch_serve(const ServeArgs &a, int waves, hipStream_t stream);
 size_t serve_lds_per_wave(int d, int vlog2);
-int search_default_vlog2(int Leff, int64_t nq);
+int search_default_vlog2(int Leff, int64_t nq, int store);
 size_t search_lds_per_wave(int Leff, int vlog2);
 
 // reduced-precision storage

@@ -8,6 +8,8 @@
 // output tile: bf16 inputs (v_mfma_f32_32x32x16_bf16) or float32 inputs
 // (v_mfma_f32_32x32x2f32, used for gradient checks), float32 accumulation.
 // Operands are read through strides, so transposed products need no copies.
+// Prediction packs the weights and inputs to bf16 once and runs the same
+// products on 16-byte fragment loads.
 // Parameters, gradients and Adam moments are float32.
 #include <hip/hip_runtime.h>
 
@@ -185,6 +187,72 @@ __global__ void adam(float *__restrict__ w, const float *__restrict__ g, float *
 
 // Entry choice: argmax of the scores (ties to the lower index) and its softmax
 // probability; below theta the navigating node is used instead.
+// ---- prediction-only products on packed bf16 operands
+// out[r * cols + c] = bf16(src[r * s0 + c * s1]): inputs row by row, weights
+// transposed so that a column's k values are contiguous.
+__global__ void pack_bf16(const float *__restrict__ src, int64_t rows, int cols, int64_t s0,
+                          int64_t s1, uint16_t *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * cols) return;
+    const int64_t r = t / cols, c = t % cols;
+    out[t] = bf16_bits(src[r * s0 + c * s1]);
+}
+
+// C = A Bt^T + bias with A [M x K] and Bt [N x K] bf16 (K a multiple of 16):
+// the same bf16 operands, k order and matrix instruction as gemm_kernel, so
+// the float32 results are identical; every fragment is one 16-byte load.  A
+// wave computes 32 x (32 NJ) outputs (the A fragment serves NJ products);
+// RELU writes relu(C) rounded to bf16 (the next layer's operand), otherwise C
+// is written in float32.
+template <int NJ, bool RELU>
+__global__ __launch_bounds__(256) void gemm_packed(const uint16_t *__restrict__ A,
+                                                   const uint16_t *__restrict__ Bt, int M, int N,
+                                                   int K, const float *__restrict__ bias,
+                                                   float *__restrict__ Cf, uint16_t *__restrict__ Cb)
+{
+    const int lane = lane_id();
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int tilesN = (N + 32 * NJ - 1) / (32 * NJ);
+    if (tile >= (int64_t)((M + 31) / 32) * tilesN) return;
+    const int i0 = (int)(tile / tilesN) * 32, j0 = (int)(tile % tilesN) * 32 * NJ;
+    const int ia = i0 + (lane & 31) < M ? i0 + (lane & 31) : M - 1;
+    const uint16_t *arow = A + (int64_t)ia * K + (lane >> 5) * 8;
+    const uint16_t *brow[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int jb = j0 + j * 32 + (lane & 31);
+        brow[j] = Bt + (int64_t)(jb < N ? jb : N - 1) * K + (lane >> 5) * 8;
+    }
+    floatx16 acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = floatx16{};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(arow + k0);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(brow[j] + k0);
+            acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int c = j0 + j * 32 + (lane & 31);
+            if (i < M && c < N) {
+                float v = acc[j][r] + bias[c];
+                if (RELU) {
+                    v = v > 0.f ? v : 0.f;
+                    Cb[(int64_t)i * N + c] = bf16_bits(v);
+                } else {
+                    Cf[(int64_t)i * N + c] = v;
+                }
+            }
+        }
+}
+
 __global__ __launch_bounds__(256) void predict_entry(const float *__restrict__ Z, int B, int K,
                                                      const uint32_t *__restrict__ entries,
                                                      uint32_t fallback, float theta,
@@ -236,10 +304,17 @@ MlpShape::MlpShape(int d_, int H_, int K_) : d(d_), H(H_), K(K_)
     total = ob3 + K;
 }
 
-size_t mlp_workspace_floats(const MlpShape &s, int B)
+static size_t mlp_base_floats(const MlpShape &s, int B)
 {
     // H1, H2, Z, dZ, dH2, dH1, loss
-    return (size_t)B * s.H * 4 + (size_t)B * s.K * 2 + (size_t)B + 64;
+    return ((size_t)B * s.H * 4 + (size_t)B * s.K * 2 + (size_t)B + 64 + 3) / 4 * 4;
+}
+
+size_t mlp_workspace_floats(const MlpShape &s, int B)
+{
+    // then, for prediction, packed bf16 weights (transposed) and inputs
+    const size_t halves = (size_t)s.d * s.H + (size_t)s.H * s.H + (size_t)s.K * s.H + (size_t)B * s.d;
+    return mlp_base_floats(s, B) + (halves + 1) / 2 + 64;
 }
 
 static GemmArgs mk(int M, int N, int K, const float *A, int64_t as0, int64_t as1, const float *B,
@@ -312,7 +387,39 @@ hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B,
                        uint32_t *out, float *conf, hipStream_t st)
 {
     float *Z = ws + (size_t)B * s.H * 2;
-    hipError_t e = mlp_forward(s, P, X, nullptr, B, bf16, ws, Z, st);
+    hipError_t e = hipSuccess;
+    if (bf16 && s.d % 16 == 0 && s.H % 16 == 0 && B > 0) {
+        // packed operands: bf16 activations in the H1 / H2 areas, weights and
+        // inputs after the training areas (every part 16-byte aligned)
+        uint16_t *H1b = reinterpret_cast<uint16_t *>(ws);
+        uint16_t *H2b = reinterpret_cast<uint16_t *>(ws + (size_t)B * s.H);
+        uint16_t *W1t = reinterpret_cast<uint16_t *>(ws + mlp_base_floats(s, B));
+        uint16_t *W2t = W1t + (size_t)s.d * s.H;
+        uint16_t *W3t = W2t + (size_t)s.H * s.H;
+        uint16_t *Xb = W3t + ((size_t)s.K * s.H + 7) / 8 * 8;
+        auto pack = [&](const float *src, int64_t rows, int cols, int64_t s0, int64_t s1, uint16_t *dst) {
+            const int64_t t = rows * cols;
+            hipLaunchKernelGGL(pack_bf16, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, src, rows,
+                               cols, s0, s1, dst);
+        };
+        pack(P + s.oW1, s.H, s.d, 1, s.H, W1t);  // W1 (k, j) = W1[k * H + j]
+        pack(P + s.oW2, s.H, s.H, 1, s.H, W2t);
+        pack(P + s.oW3, s.K, s.H, 1, s.K, W3t);  // W3 (k, j) = W3[k * K + j]
+        pack(X, B, s.d, s.d, 1, Xb);
+        auto grid = [&](int N) {
+            const int64_t tiles = (int64_t)((B + 31) / 32) * ((N + 127) / 128);
+            return dim3((unsigned)((tiles + 3) / 4));
+        };
+        hipLaunchKernelGGL((gemm_packed<4, true>), grid(s.H), dim3(256), 0, st, Xb, W1t, B, s.H, s.d,
+                           P + s.ob1, nullptr, H1b);
+        hipLaunchKernelGGL((gemm_packed<4, true>), grid(s.H), dim3(256), 0, st, H1b, W2t, B, s.H, s.H,
+                           P + s.ob2, nullptr, H2b);
+        hipLaunchKernelGGL((gemm_packed<4, false>), grid(s.K), dim3(256), 0, st, H2b, W3t, B, s.K, s.H,
+                           P + s.ob3, Z, nullptr);
+        e = hipGetLastError();
+    } else {
+        e = mlp_forward(s, P, X, nullptr, B, bf16, ws, Z, st);
+    }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(predict_entry, dim3((B + 3) / 4), dim3(256), 0, st, Z, B, s.K, entries,
                        fallback, theta, out, conf);

@@ -518,17 +518,19 @@ size_t search_lds_per_wave(int Leff, int vlog2)
     return wave_lds_bytes(64 * qs, vlog2);
 }
 
-// Visited-table slots (log2) of a launch of nq queries when the caller leaves
-// them open.  With more queries than the GPU holds at once, 2048 slots up to
-// L = 128 and 1024 beyond: a small LDS share keeps more waves resident, and
-// longer searches need it more (measured, 1M x 128 and 10M x 128 with 10k
-// queries: 2048 slots 1-2 % faster than 1024 at L = 64 .. 96, 1024 slots 3 %
-// to 74 % faster than 2048 or 4096 at L = 144 .. 512; 512 slots slower
-// everywhere).  When every query's wave fits at once, the largest table up to
-// 8192 slots that still lets them all be resident: fewer forgotten vectors to
-// read again (1M x 960, 1000 queries, L = 352: 8192 slots 9 % faster than
-// 4096).
-int search_default_vlog2(int Leff, int64_t nq)
+// Visited-table slots (log2) of a launch of nq queries over vectors stored as
+// `store` (0 float32, 1 bf16, 2 fp8) when the caller leaves them open.  With
+// more queries than the GPU holds at once, 1024 slots, or 2048 for float32 up
+// to L = 128: a small LDS share keeps more waves resident, and longer or
+// lighter (reduced-precision) searches need that most (measured, 1M x 128 and
+// 10M x 128 with 10k queries: float32 2048 slots 1-2 % faster than 1024 at
+// L = 64 .. 96, 1024 slots 3 % to 74 % faster than 2048 or 4096 at
+// L = 144 .. 512; bf16 at L = 80 17 % slower with 2048 than with 1024; 512
+// slots slower everywhere).  When every query's wave fits at once, the largest
+// table up to 8192 slots that still lets them all be resident: fewer forgotten
+// vectors to read again (1M x 960, 1000 queries, L = 352: 8192 slots 9 %
+// faster than 4096).
+int search_default_vlog2(int Leff, int64_t nq, int store)
 {
     const size_t lds_cu = 160 * 1024;
     for (int vl = 13; vl > 10; --vl) {
@@ -537,7 +539,7 @@ int search_default_vlog2(int Leff, int64_t nq)
         if (waves > 32) waves = 32;
         if (256 * waves >= nq) return vl;
     }
-    return Leff <= 128 ? 11 : 10;
+    return store == 0 && Leff <= 128 ? 11 : 10;
 }
 
 hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
