@@ -217,3 +217,14 @@ def test_knn_locality_order_overflow_and_duplicates():
     ids, D, _ = gpu_knn(x, x, 40, True)
     oids, oD = oracle.knn(x, x, 40, exclude_self=True)
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_knn_largest_band(cfg):
+    """The largest band the interface accepts (2048 entries per row) fits every
+    filter form's LDS: split bf16, exact bf16 and the streamed d > 128 form."""
+    x, _ = workloads.generate(cfg, n=2500 if cfg != 3 else 1100, nq=1)
+    ids, D, ovf = gpu_knn(x, x, 64, True, band=2048)
+    assert ovf == 0
+    oids, oD = oracle.knn(x, x, 64, exclude_self=True)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
