@@ -93,3 +93,24 @@ def test_other_stages_reject():
     assert L.cng_connect(fake, 10, 8, fake, 4, 10, 8, 0, fake, 1 << 30, None, None, None) == -1
     # workspace too small
     assert L.cng_entry_point(fake, 10, 8, fake, fake, 1, None) == -2
+
+
+def test_serve_config_rejected_before_any_device_call():
+    from paper_2510_05975_amd._lib import ServeConfig
+    L = cng.lib()
+    fake = 0x1000
+    out = C.c_void_p(0)
+
+    def start(**kw):
+        f = dict(points=fake, vecs=fake, dtype=0, scales=None, n=100, d=8, adj=fake, W=4, entry=0,
+                 waves=0, capacity=0, max_k=10, visited_log2=0)
+        f.update(kw)
+        cfg = ServeConfig(*[f[k] for k, _ in ServeConfig._fields_])
+        return L.cng_serve_start(C.byref(cfg), C.c_void_p(fake), 1 << 20, C.byref(out))
+
+    assert start(visited_log2=14) == -1   # 6 .. 13 or 0
+    assert start(visited_log2=5) == -1
+    assert start(d=6) == -4               # d % 4
+    assert start(max_k=300) == -4
+    assert start(entry=100) == -1
+    assert start(dtype=2) == -1           # fp8 without scales
