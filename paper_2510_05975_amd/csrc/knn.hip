@@ -13,10 +13,10 @@
 // overflow on the next tile it is compacted: cut to F <= F_C + 2E, where F_C
 // is the C-th smallest F so far and E bounds |F - (D - |x|^2)| for every
 // column of this row (the product and norm rounding of the filter plus the
-// rounding of D itself).  Any
-// point of the exact top C then satisfies F <= F_C + 2E, so the band always
-// contains it.  With small-integer data every quantity is an exact integer and
-// E = 0.
+// rounding of D itself).  Any point of the exact top C then satisfies
+// F <= F_C + 2E, so the band always contains it.  With small-integer data every
+// quantity is an exact integer and E = 0.  Self-joins with d <= 128 sweep the
+// columns in a locality order (see the locality order section below).
 // Stage 2, rerank: D is recomputed for the band in the fixed order and the top
 // C by (D, id) is selected by a bitonic sort.
 // Stage 3: rows whose band overflowed are recomputed exhaustively.
