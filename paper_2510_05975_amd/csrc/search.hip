@@ -87,12 +87,13 @@ __device__ __forceinline__ int lower_bound_keys(const uint64_t *arr, int cnt, ui
 template <int G, int RND, bool VEC, int UB, int ST>
 __device__ __forceinline__ void gather_dists(const void *__restrict__ vecs, const float *__restrict__ scales,
                                              int d, const uint32_t *cid, int m, const float4 (&qr)[RND],
-                                             float *dsc)
+                                             float *dsc, int part = 0, int parts = 1)
 {
     constexpr int NG = 64 / G;
     const int lane = lane_id();
     const int grp = lane / G, gl = lane % G;
-    for (int b = 0; b < m; b += NG * UB) {
+    // batches part, part + parts, ... of the list (several waves may share it)
+    for (int b = part * NG * UB; b < m; b += parts * NG * UB) {
         // Loads only: nothing in a guarded block uses a loaded value, so no
         // wait separates the loads of a batch.  A group past the end of the
         // list re-reads vector b and its sum is never written.
@@ -146,6 +147,7 @@ struct WaveLds {
     uint64_t *qa, *tmp;
     float *dsc;
     uint32_t *cid, *vis;
+    int *ctl;  // cooperative searches: the list length handed to the helper waves
 };
 
 __host__ __device__ constexpr size_t wave_lds_bytes(int qcap, int vlog2)
@@ -154,7 +156,10 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int qcap, int vlog2)
 }
 
 // One query.  G lanes per vector, RND float4 rounds per lane, QS beam slots per lane.
-template <int G, int RND, bool VEC, int QS, int UB, int ST>
+// COOP > 1: the query's wave is the first of a workgroup of COOP waves; the
+// others (coop_helper) compute a share of every distance batch.  Each batch
+// costs the workgroup two barriers, matched one for one by the helpers.
+template <int G, int RND, bool VEC, int QS, int UB, int ST, int COOP = 1>
 __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
 {
     const int lane = lane_id();
@@ -224,7 +229,14 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
             }
             wave_sync();
             // ---- distances: G lanes per vector, NG vectors per instruction
-            gather_dists<G, RND, VEC, UB, ST>(a.vecs, a.scales, d, s.cid, m, qr, s.dsc);
+            if constexpr (COOP > 1) {
+                if (lane == 0) s.ctl[0] = m;
+                __syncthreads();  // the list and its length are visible to the helpers
+                gather_dists<G, RND, VEC, UB, ST>(a.vecs, a.scales, d, s.cid, m, qr, s.dsc, 0, COOP);
+                __syncthreads();  // every share of the distances is in dsc
+            } else {
+                gather_dists<G, RND, VEC, UB, ST>(a.vecs, a.scales, d, s.cid, m, qr, s.dsc);
+            }
             wave_sync();
             ndc += (uint32_t)m;
             // ---- merge the m new keys into the beam (Algorithm 1: union, keep the L closest)
@@ -329,6 +341,44 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a)
     beam_query<G, RND, VEC, QS, UB, ST>(a, qi, s);
 }
 
+// One query per workgroup of four waves: wave 0 runs the search, waves 1..3
+// compute their share of each distance batch.  For launches of few queries
+// with long vectors, where a hop waits on several rounds of vector loads.
+template <int G, int RND, bool VEC, int QS, int UB>
+__global__ __launch_bounds__(256) void search_coop_kernel(SearchArgs a)
+{
+    constexpr int COOP = 4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = threadIdx.x >> 6;
+    const int64_t qi = blockIdx.x;  // the grid has exactly nq workgroups
+    const int qcap = 64 * QS;
+    WaveLds s;
+    s.qa = reinterpret_cast<uint64_t *>(smem);
+    s.tmp = s.qa + qcap;
+    s.dsc = reinterpret_cast<float *>(s.tmp + 64);
+    s.cid = reinterpret_cast<uint32_t *>(s.dsc + 64);
+    s.vis = s.cid + 64;
+    s.ctl = reinterpret_cast<int *>(s.vis + ((size_t)1 << a.vlog2));
+    if (wave == 0) {
+        beam_query<G, RND, VEC, QS, UB, 0, COOP>(a, qi, s);
+        if (lane_id() == 0) s.ctl[0] = -1;
+        __syncthreads();  // releases the helpers
+        return;
+    }
+    const int gl = lane_id() % G;
+    const float *qv = a.query_ids ? a.points + (size_t)a.query_ids[qi] * a.d : a.queries + (size_t)qi * a.d;
+    float4 qr[RND];
+#pragma unroll
+    for (int r = 0; r < RND; ++r) qr[r] = load_chunk<VEC>(qv, a.d, r, gl);
+    for (;;) {
+        __syncthreads();  // a list from wave 0, or the end of the search
+        const int m = s.ctl[0];
+        if (m < 0) break;
+        gather_dists<G, RND, VEC, UB, 0>(a.vecs, a.scales, a.d, s.cid, m, qr, s.dsc, wave, COOP);
+        __syncthreads();
+    }
+}
+
 using KernelFn = void (*)(SearchArgs);
 
 template <int G, int RND, bool VEC, int ST, int UBX = 0>
@@ -362,6 +412,24 @@ KernelFn pick_kernel(int d, int qs, bool deep)
     if (rnd <= 8) return pick_qs<32, 8, VEC, ST>(qs);
     if (rnd <= 16) return pick_qs<32, 16, VEC, ST>(qs);
     return pick_qs<32, 32, VEC, ST>(qs);
+}
+
+template <int G, int RND, bool VEC, int UB>
+KernelFn pick_coop_qs(int qs)
+{
+    switch (qs) {
+    case 1: return search_coop_kernel<G, RND, VEC, 1, UB>;
+    case 2: return search_coop_kernel<G, RND, VEC, 2, UB>;
+    case 4: return search_coop_kernel<G, RND, VEC, 4, UB>;
+    default: return search_coop_kernel<G, RND, VEC, 8, UB>;
+    }
+}
+
+// float32, 257 <= d <= 1024 (rnd 3 .. 8), with the deep load batches
+template <bool VEC>
+KernelFn pick_coop(int rnd, int qs)
+{
+    return rnd <= 4 ? pick_coop_qs<32, 4, VEC, 8>(qs) : pick_coop_qs<32, 8, VEC, 4>(qs);
 }
 
 template <bool VEC>
@@ -551,6 +619,16 @@ hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
                      ((uintptr_t)a.vecs % vbytes == 0) &&
                      (a.query_ids || (uintptr_t)a.queries % 16 == 0);
     const bool deep = a.nq <= 1024;
+    const int rnd = (a.d + 127) / 128;
+    if (a.store == 0 && a.nq <= 256 && rnd > 2 && rnd <= 8) {
+        // few float32 queries with long vectors: four waves per query
+        KernelFn cf = vec ? pick_coop<true>(rnd, qs) : pick_coop<false>(rnd, qs);
+        SearchArgs b = a;
+        while (b.vlog2 > 6 && wave_lds_bytes(64 * qs, b.vlog2) + 16 > 64 * 1024) --b.vlog2;
+        hipLaunchKernelGGL(cf, dim3((unsigned)a.nq), dim3(256),
+                           (unsigned)(wave_lds_bytes(64 * qs, b.vlog2) + 16), stream, b);
+        return hipGetLastError();
+    }
     KernelFn fn = vec ? pick_store<true>(a.d, qs, a.store, deep) : pick_store<false>(a.d, qs, a.store, deep);
     // the visited table may be shrunk to keep a wave within 64 KB of LDS
     // (it only changes how often a distance is recomputed, never the results)
