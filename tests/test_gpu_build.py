@@ -228,3 +228,13 @@ def test_knn_largest_band(cfg):
     assert ovf == 0
     oids, oD = oracle.knn(x, x, 64, exclude_self=True)
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+def test_knn_same_size_different_arrays():
+    """As many queries as points but different arrays: not a self-join (no
+    locality order, no self exclusion)."""
+    x, _ = workloads.generate(1, n=2500, nq=1)
+    q, _ = workloads.generate(1, n=2500, nq=1, seed=4)
+    ids, D, _ = gpu_knn(q, x, 16, False)
+    oids, oD = oracle.knn(q, x, 16)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))

@@ -132,3 +132,19 @@ def test_sift_like_reduced():
     adj, e, _ = oracle.build(x, 32, 128, 1.2)
     for L in (16, 64):
         assert_same(gpu_search(x, adj, q, 10, L, e), oracle.search(x, adj, q, 10, L, e))
+
+
+def test_four_wave_search_edge_cases():
+    """Few queries with d > 256 run four waves per query: per-query entries,
+    an invalid entry (nothing reachable: the query's wave leaves at once and
+    releases its helpers), k above L."""
+    x, q = workloads.uniform_cube(900, 6, 300, seed=11)
+    adj, e, _ = oracle.build(x, 10, 20, 1.2)
+    ents = np.array([e, 5, 17, 899, 900, 3], np.uint32)   # 900 >= n: invalid
+    ids, d, _, _ = gpu_search(x, adj, q, 12, 8, ents)
+    for i in range(len(q)):
+        if ents[i] >= len(x):
+            assert (ids[i] == oracle.NONE).all() and np.isinf(d[i]).all()
+            continue
+        o = oracle.search(x, adj, q[i:i + 1], 12, 8, int(ents[i]))
+        assert (ids[i] == o[0][0]).all() and same_f32(d[i:i + 1], f32_of(o[1]))
