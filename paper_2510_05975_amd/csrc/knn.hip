@@ -615,27 +615,30 @@ __device__ __forceinline__ bool append_tile(const FilterArgs &a, const floatx16 
                              std::make_integer_sequence<int, NJ>{});
 }
 
-// After a tile (every thread of the workgroup): when a band of the workgroup
-// passed the trigger, or after the last tile, the register counts go to LDS,
-// the bands that need it are compacted, and counts and thresholds come back.
-// An overflowed row (count -1) keeps the OVERFLOWED marker and takes nothing
-// more.
+// After a tile (every thread of the workgroup): the barrier that publishes the
+// next column tile; then a wave one of whose bands passed the trigger (and
+// every wave after the last tile) compacts its own rows' bands that need it:
+// only that wave appends to them, so no other wave has to wait for it here
+// (measured: 262144 x 960 candidate search 0.633 -> 0.605 s against a
+// workgroup-wide compaction step; neutral at d = 128).  An overflowed row
+// (count -1) keeps the OVERFLOWED marker and takes nothing more.
 constexpr uint32_t OVERFLOWED = 0xFFFFFFFFu;
 
 template <int BN, bool STAGE>
-__device__ __forceinline__ void settle_bands(const FilterArgs &a, bool wflag, bool last, int *flag,
-                                             int *cnt, float *thr, const float *erow, uint32_t *keys,
+__device__ __forceinline__ void settle_bands(const FilterArgs &a, bool wflag, bool last, int *cnt,
+                                             float *thr, const float *erow, uint32_t *keys,
                                              uint32_t *hist, uint32_t rowstart, uint32_t &mypos,
                                              float (&th)[2][16])
 {
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int trig = a.CB - BN;
-    if (wflag && lane == 0) flag[0] = 1;
     lds_barrier();
-    if (flag[0] || last) {
+    if (wflag || last) {  // uniform across the wave
+        // this wave's band stores complete before its lanes read them back
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         cnt[wave * 64 + lane] = mypos == OVERFLOWED ? -1 : (int)(mypos - rowstart);
-        __syncthreads();  // band stores and counts of every wave complete
-        for (int li = wave; li < BM2; li += 4) {
+        wave_sync();
+        for (int li = wave * 64; li < wave * 64 + 64; ++li) {
             const int c = cnt[li];
             const bool need = c >= 0 && (last ? c > a.C : c > trig);
             if (need)
@@ -643,15 +646,14 @@ __device__ __forceinline__ void settle_bands(const FilterArgs &a, bool wflag, bo
                                     keys + (size_t)wave * (STAGE ? 2 : 1) * a.CB, hist + wave * 256,
                                     last, BN);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) flag[0] = 0;
+        wave_sync();
         {
             const int c = cnt[wave * 64 + lane];
             mypos = c < 0 ? OVERFLOWED : rowstart + (uint32_t)c;
         }
         load_thr(th, thr);
-        __syncthreads();
     }
+    if (last) __syncthreads();  // every row's final count is in LDS
 }
 
 // SPLIT (general float data): every value is the sum of two bf16 numbers,
@@ -672,8 +674,7 @@ void filter_bf16(FilterBf16Args A)
     float *thr = nys + 2 * BN2;                                     // BM2
     float *erow = thr + BM2;
     int *cnt = reinterpret_cast<int *>(erow + BM2);                // band counts, during compaction
-    int *flag = cnt + BM2;                                          // [0]: a band needs compaction
-    uint32_t *hist = reinterpret_cast<uint32_t *>(flag + 4);        // 4 x 256
+    uint32_t *hist = reinterpret_cast<uint32_t *>(cnt + BM2);       // 4 x 256
     uint32_t *keys = hist + 4 * 256;                                // 4 x CB
 
     const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -687,7 +688,6 @@ void filter_bf16(FilterBf16Args A)
         erow[li] = live ? a.E[gi] : 0.f;
         cnt[li] = 0;
     }
-    if (threadIdx.x == 0) flag[0] = 0;
     // Next free band slot of row wave * 64 + lane, as an offset into the band
     // arrays (a pass holds at most 2^28 entries).  A wave alone appends to its
     // 64 rows, so these live in a register, read and written per row by lane
@@ -823,7 +823,7 @@ void filter_bf16(FilterBf16Args A)
 #pragma unroll
         for (int j = 0; j < 2; ++j) nyv[j] = nys[buf * BN2 + j * 32 + (lane & 31)];
         const bool wflag = append_tile<2>(a, acc, nyv, th, nullptr, col0, trig, mypos);
-        settle_bands<BN2, false>(a, wflag, !more, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
+        settle_bands<BN2, false>(a, wflag, !more, cnt, thr, erow, keys, hist, rowstart, mypos, th);
         buf ^= 1;
         col0 = next0;
     }
@@ -839,7 +839,7 @@ void filter_bf16(FilterBf16Args A)
 size_t filter_bf16_lds_bytes(int K, int CB, bool split)
 {
     return (size_t)2 * (split ? 2 : 1) * BN2 * (K + 8) * 2 + (size_t)2 * BN2 * 4 +
-           (size_t)BM2 * 4 * 3 + 16 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
+           (size_t)BM2 * 4 * 3 + (size_t)4 * 256 * 4 + (size_t)4 * CB * 4;
 }
 
 // ---------------------------------------------------------------- wide bf16 filter
@@ -870,8 +870,7 @@ void filter_wide(FilterBf16Args A, int K)
     float *thr = reinterpret_cast<float *>(Bs + 2 * NP * BNW * BSTR);
     float *erow = thr + BM2;
     int *cnt = reinterpret_cast<int *>(erow + BM2);
-    int *flag = cnt + BM2;
-    uint32_t *hist = reinterpret_cast<uint32_t *>(flag + 4);  // 4 x 256
+    uint32_t *hist = reinterpret_cast<uint32_t *>(cnt + BM2);  // 4 x 256
     uint32_t *keys = hist + 4 * 256;                          // 4 x 2 CB
 
     const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -884,7 +883,6 @@ void filter_wide(FilterBf16Args A, int K)
         erow[li] = live ? a.E[gi] : 0.f;
         cnt[li] = 0;
     }
-    if (threadIdx.x == 0) flag[0] = 0;
     const uint32_t rowstart = (uint32_t)(blockIdx.x * BM2 + wave * 64 + lane) * (uint32_t)a.CB;
     const int trig = a.CB - BNW;
     uint32_t mypos = rowstart;
@@ -1006,7 +1004,7 @@ void filter_wide(FilterBf16Args A, int K)
             lds_barrier();
         }
         const bool wflag = append_tile<NJ>(a, acc, nyv, th, thr, col0, trig, mypos);
-        settle_bands<BNW, true>(a, wflag, !more_tiles, flag, cnt, thr, erow, keys, hist, rowstart, mypos, th);
+        settle_bands<BNW, true>(a, wflag, !more_tiles, cnt, thr, erow, keys, hist, rowstart, mypos, th);
         col0 = next0;
     }
     for (int li = threadIdx.x; li < BM2; li += 256) {
@@ -1027,7 +1025,7 @@ constexpr int WPEW = 1;   // waves per SIMD
 
 size_t filter_wide_lds_bytes(int CB, bool split)
 {
-    return (size_t)2 * (split ? 2 : 1) * BNW * (KCW + 8) * 2 + (size_t)BM2 * 4 * 3 + 16 +
+    return (size_t)2 * (split ? 2 : 1) * BNW * (KCW + 8) * 2 + (size_t)BM2 * 4 * 3 +
            (size_t)4 * 256 * 4 + (size_t)4 * CB * 8;
 }
 
