@@ -238,3 +238,29 @@ def test_knn_same_size_different_arrays():
     ids, D, _ = gpu_knn(q, x, 16, False)
     oids, oD = oracle.knn(q, x, 16)
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+@pytest.mark.parametrize("d", [32, 200])
+def test_knn_waves_compact_at_different_times(d):
+    """One wave's rows (rows 64-127 of the first 256-row block) take nearly every
+    column: past the first 256 columns each base point is closer to them than
+    all earlier ones.  The other rows find their nearest points in the first
+    tiles and settle there.  Each wave compacts its own bands on its own
+    schedule; the last block is ragged (77 rows)."""
+    g = np.random.default_rng(11 + d)
+    n = 3000
+    anchor = np.zeros(d)
+    anchor[0] = 200.0
+    y = np.empty((n, d))
+    y[:256] = anchor + g.standard_normal((256, d))
+    dirs = g.standard_normal((n - 256, d))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    y[256:] = dirs * np.linspace(50.0, 1.0, n - 256)[:, None]
+    q = anchor + g.standard_normal((333, d))
+    q[64:128] = g.standard_normal((64, d)) * 1e-3
+    y, q = y.astype(np.float32), q.astype(np.float32)
+    ids, D, _ = gpu_knn(q, y, 64, False)
+    oids, oD = oracle.knn(q, y, 64)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+    assert (ids[64:128] >= n - 64).all()  # the points closest to the origin come last
+    assert (ids[:64] < 256).all() and (ids[128:] < 256).all()
