@@ -482,29 +482,47 @@ __device__ __forceinline__ uint16_t to_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
-// x [n x d] float32 -> [n x K] bf16, zero padded to K; row r of the output is
-// row order[r] of x (order may be null: the identity).
-__global__ void to_bf16_padded(const float *__restrict__ x, int64_t n, int d, int K,
+// Output element t of an n-row bf16 copy with K values per row -> (row r, value
+// k): row-major [n x K] when blk = 0, else k-blocked [K / blk][n][blk] (the
+// streamed filter reads blk values of many rows per stage, and in this layout
+// they are whole, contiguous cache lines).  K is a multiple of blk.
+__device__ __forceinline__ void copy_pos(int64_t t, int64_t n, int K, int blk, int64_t &r, int &k)
+{
+    if (blk) {
+        const int64_t nb = n * blk, kb = t / nb, rem = t - kb * nb;
+        r = rem / blk;
+        k = (int)(kb * blk + rem % blk);
+    } else {
+        r = t / K;
+        k = (int)(t % K);
+    }
+}
+
+// x [n x d] float32 -> bf16 copy, zero padded to K values per row; row r of the
+// copy is row order[r] of x (order may be null: the identity)
+__global__ void to_bf16_padded(const float *__restrict__ x, int64_t n, int d, int K, int blk,
                                uint16_t *__restrict__ out, const uint32_t *__restrict__ order)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * K) return;
-    int64_t r = t / K;
-    int k = (int)(t % K);
+    int64_t r;
+    int k;
+    copy_pos(t, n, K, blk, r, k);
     if (order) r = order[r];
     out[t] = k < d ? to_bf16_rne(x[(size_t)r * d + k]) : (uint16_t)0;
 }
 
-// x [n x d] float32 -> hi = bf16(x), lo = bf16(x - hi), [n x K] each, zero padded
-// (x - hi is exact in float32); rows in `order` as above
-__global__ void to_bf16_split(const float *__restrict__ x, int64_t n, int d, int K,
+// x [n x d] float32 -> hi = bf16(x), lo = bf16(x - hi), laid out as above, zero
+// padded (x - hi is exact in float32); rows in `order` as above
+__global__ void to_bf16_split(const float *__restrict__ x, int64_t n, int d, int K, int blk,
                               uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
                               const uint32_t *__restrict__ order)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * K) return;
-    int64_t r = t / K;
-    int k = (int)(t % K);
+    int64_t r;
+    int k;
+    copy_pos(t, n, K, blk, r, k);
     if (order) r = order[r];
     const float v = k < d ? x[(size_t)r * d + k] : 0.f;
     const uint16_t h = to_bf16_rne(v);
@@ -512,12 +530,13 @@ __global__ void to_bf16_split(const float *__restrict__ x, int64_t n, int d, int
     lo[t] = to_bf16_rne(v - __uint_as_float((uint32_t)h << 16));
 }
 
+// bf16 copies: [n x K] for filter_bf16, k-blocked [K / KCW][n][KCW] for filter_wide
 struct FilterBf16Args {
     FilterArgs f;
-    const uint16_t *rows16;    // [nr x K]
-    const uint16_t *cols16;    // [nc x K]
-    const uint16_t *rows16lo;  // split mode: bf16 of x - hi, [nr x K]
-    const uint16_t *cols16lo;  // [nc x K]
+    const uint16_t *rows16;    // nr rows
+    const uint16_t *cols16;    // nc rows
+    const uint16_t *rows16lo;  // split mode: bf16 of x - hi, nr rows
+    const uint16_t *cols16lo;  // nc rows
 };
 
 // LDS-only barrier: the band stores of the epilogue need not be complete here
@@ -887,14 +906,16 @@ void filter_wide(FilterBf16Args A, int K)
     const int trig = a.CB - BNW;
     uint32_t mypos = rowstart;
 
-    // element offsets of this lane's row fragments; rows past the end read the
-    // last row (a dead row never takes a column), so every load is unconditional
+    // The bf16 copies are k-blocked, [K / KC][rows][KC]: stage k0 of row g
+    // starts at k0 * rows + g * KC.  Element offsets of this lane's row
+    // fragments within a stage; rows past the end read the last row (a dead
+    // row never takes a column), so every load is unconditional.
     size_t aoff[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         int64_t gi = row0 + wave * 64 + i * 32 + (lane & 31);
         gi = gi < rend ? gi : rend - 1;
-        aoff[i] = (size_t)gi * K + (lane >> 5) * 8;
+        aoff[i] = (size_t)gi * KC + (lane >> 5) * 8;
     }
     bf16x8 a0[2][KSS][NP], a1[2][KSS][NP];
     auto fetch_a = [&](bf16x8 (&dst)[2][KSS][NP], int k0) {
@@ -902,10 +923,9 @@ void filter_wide(FilterBf16Args A, int K)
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int ks = 0; ks < KSS; ++ks) {
-                dst[i][ks][0] = *reinterpret_cast<const bf16x8 *>(A.rows16 + aoff[i] + k0 + ks * 16);
-                if constexpr (SPLIT)
-                    dst[i][ks][NP - 1] =
-                        *reinterpret_cast<const bf16x8 *>(A.rows16lo + aoff[i] + k0 + ks * 16);
+                const size_t o = (size_t)k0 * a.nr + aoff[i] + ks * 16;
+                dst[i][ks][0] = *reinterpret_cast<const bf16x8 *>(A.rows16 + o);
+                if constexpr (SPLIT) dst[i][ks][NP - 1] = *reinterpret_cast<const bf16x8 *>(A.rows16lo + o);
             }
     };
     // column tile stage: columns past the end read the last column (their F
@@ -920,7 +940,7 @@ void filter_wide(FilterBf16Args A, int K)
             int64_t gj = col0 + col;
             gj = gj < a.nc ? gj : a.nc - 1;
             const uint16_t *src = (SPLIT && part) ? A.cols16lo : A.cols16;
-            pre[i] = *reinterpret_cast<const u32x4 *>(src + (size_t)gj * K + k0 + kc * 8);
+            pre[i] = *reinterpret_cast<const u32x4 *>(src + (size_t)k0 * a.nc + (size_t)gj * KC + kc * 8);
         }
     };
     auto stash = [&](int buf) {
@@ -1487,18 +1507,19 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     }
     if (use_bf16 || use_split) {
         const int64_t tc = nc * K16, tr = nr * K16;
+        const int blk = wide ? KCW : 0;  // the streamed filter reads k-blocked copies
         if (use_bf16) {
             hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0,
-                               stream, cols, nc, d, K16, cols16, ord);
+                               stream, cols, nc, d, K16, blk, cols16, ord);
             if (!self)
                 hipLaunchKernelGGL(to_bf16_padded, dim3((unsigned)((tr + 255) / 256)), dim3(256), 0,
-                                   stream, rows, nr, d, K16, rows16, nullptr);
+                                   stream, rows, nr, d, K16, blk, rows16, nullptr);
         } else {
             hipLaunchKernelGGL(to_bf16_split, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0,
-                               stream, cols, nc, d, K16, cols16, cols16lo, ord);
+                               stream, cols, nc, d, K16, blk, cols16, cols16lo, ord);
             if (!self)
                 hipLaunchKernelGGL(to_bf16_split, dim3((unsigned)((tr + 255) / 256)), dim3(256), 0,
-                                   stream, rows, nr, d, K16, rows16, rows16lo, nullptr);
+                                   stream, rows, nr, d, K16, blk, rows16, rows16lo, nullptr);
         }
         if (self) {
             rows16 = cols16;
