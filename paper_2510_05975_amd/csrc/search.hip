@@ -341,13 +341,16 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a)
     beam_query<G, RND, VEC, QS, UB, ST>(a, qi, s);
 }
 
-// One query per workgroup of four waves: wave 0 runs the search, waves 1..3
+// Waves per workgroup of the cooperative search (one query per workgroup).
+constexpr int COOPW = 8;
+
+// One query per workgroup of COOPW waves: wave 0 runs the search, the others
 // compute their share of each distance batch.  For launches of few queries
 // with long vectors, where a hop waits on several rounds of vector loads.
 template <int G, int RND, bool VEC, int QS, int UB>
-__global__ __launch_bounds__(256) void search_coop_kernel(SearchArgs a)
+__global__ __launch_bounds__(64 * COOPW) void search_coop_kernel(SearchArgs a)
 {
-    constexpr int COOP = 4;
+    constexpr int COOP = COOPW;
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6;
     const int64_t qi = blockIdx.x;  // the grid has exactly nq workgroups
@@ -621,11 +624,11 @@ hipError_t launch_search(const SearchArgs &a, hipStream_t stream)
     const bool deep = a.nq <= 1024;
     const int rnd = (a.d + 127) / 128;
     if (a.store == 0 && a.nq <= 256 && rnd > 2 && rnd <= 8) {
-        // few float32 queries with long vectors: four waves per query
+        // few float32 queries with long vectors: COOPW waves per query
         KernelFn cf = vec ? pick_coop<true>(rnd, qs) : pick_coop<false>(rnd, qs);
         SearchArgs b = a;
         while (b.vlog2 > 6 && wave_lds_bytes(64 * qs, b.vlog2) + 16 > 64 * 1024) --b.vlog2;
-        hipLaunchKernelGGL(cf, dim3((unsigned)a.nq), dim3(256),
+        hipLaunchKernelGGL(cf, dim3((unsigned)a.nq), dim3(64 * COOPW),
                            (unsigned)(wave_lds_bytes(64 * qs, b.vlog2) + 16), stream, b);
         return hipGetLastError();
     }

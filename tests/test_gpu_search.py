@@ -134,8 +134,8 @@ def test_sift_like_reduced():
         assert_same(gpu_search(x, adj, q, 10, L, e), oracle.search(x, adj, q, 10, L, e))
 
 
-def test_four_wave_search_edge_cases():
-    """Few queries with d > 256 run four waves per query: per-query entries,
+def test_cooperative_search_edge_cases():
+    """Few queries with d > 256 run several waves per query: per-query entries,
     an invalid entry (nothing reachable: the query's wave leaves at once and
     releases its helpers), k above L."""
     x, q = workloads.uniform_cube(900, 6, 300, seed=11)
