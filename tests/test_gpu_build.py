@@ -64,6 +64,23 @@ def test_knn_queries_vs_points_ragged_wide():
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
 
 
+@pytest.mark.parametrize("d,lo,hi", [(200, None, None), (200, 0, 100)])
+def test_knn_more_rows_than_columns_wide(d, lo, hi):
+    """d > 128 with 700 query rows against 300 columns: the streamed filter's
+    row and column copies are k-blocked with different row counts (split form
+    for float values, exact bf16 for small integers)."""
+    g = np.random.default_rng(d + 7)
+    if lo is None:
+        x = g.standard_normal((300, d)).astype(np.float32)
+        q = g.standard_normal((700, d)).astype(np.float32)
+    else:
+        x = g.integers(lo, hi, size=(300, d)).astype(np.float32)
+        q = g.integers(lo, hi, size=(700, d)).astype(np.float32)
+    ids, D, _ = gpu_knn(q, x, 24, False)
+    oids, oD = oracle.knn(q, x, 24)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
 @pytest.mark.parametrize("d", [1, 3, 7, 33, 100, 129, 136, 200, 300])
 def test_knn_dims(d):
     x, _ = workloads.uniform_cube(700, 1, d, seed=d)
