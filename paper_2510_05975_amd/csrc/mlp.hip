@@ -154,21 +154,44 @@ __global__ __launch_bounds__(256) void softmax_xent(const float *__restrict__ Z,
 }
 
 // Column sums (bias gradients), one thread per column, rows in order.
-__global__ void colsum(const float *__restrict__ X, int B, int N, float *__restrict__ out)
+// Column sums of X [B x N] (the bias gradients): a workgroup of 16 waves owns
+// 64 columns (lane = column); wave w sums rows w, w + 16, ..., and the 16
+// partial sums are added in wave order (a fixed order: the same bits on every
+// run).
+constexpr int COLSUM_WAVES = 16;
+__global__ __launch_bounds__(64 * COLSUM_WAVES) void colsum(const float *__restrict__ X, int B, int N,
+                                                           float *__restrict__ out)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+    __shared__ float part[COLSUM_WAVES][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int i = 0; i < B; ++i) s += X[(int64_t)i * N + j];
-    out[j] = s;
+    if (j < N) {
+#pragma unroll 8
+        for (int i = w; i < B; i += COLSUM_WAVES) s += X[(int64_t)i * N + j];
+    }
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < N) {
+        float t = 0.f;
+        for (int k = 0; k < COLSUM_WAVES; ++k) t += part[k][lane];
+        out[j] = t;
+    }
 }
 
-__global__ void mean_of(const float *__restrict__ x, int n, float *__restrict__ out)
+// Mean of x [n] in float64: strided partial sums per thread, then a fixed tree.
+__global__ __launch_bounds__(256) void mean_of(const float *__restrict__ x, int n, float *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double part[256];
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += x[i];
-    *out = (float)(s / n);
+    for (int i = threadIdx.x; i < n; i += 256) s += x[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (float)(part[0] / n);
 }
 
 __global__ void adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
@@ -352,24 +375,24 @@ hipError_t mlp_gradients(const MlpShape &s, const float *P, const float *X, cons
     hipError_t e = mlp_forward(s, P, X, idx, B, bf16, ws, Z, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(softmax_xent, dim3((B + 3) / 4), dim3(256), 0, st, Z, lab, idx, B, s.K, dZ, loss);
-    if (loss_mean) hipLaunchKernelGGL(mean_of, dim3(1), dim3(1), 0, st, loss, B, loss_mean);
+    if (loss_mean) hipLaunchKernelGGL(mean_of, dim3(1), dim3(256), 0, st, loss, B, loss_mean);
     // layer 3: dW3 = H2^T dZ, db3 = colsum dZ, dH2 = (dZ W3^T) * (H2 > 0)
     e = gemm(mk(s.H, s.K, B, H2, 1, s.H, dZ, s.K, 1, G + s.oW3, nullptr, nullptr, 0), bf16, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum, dim3((s.K + 255) / 256), dim3(256), 0, st, dZ, B, s.K, G + s.ob3);
+    hipLaunchKernelGGL(colsum, dim3((s.K + 63) / 64), dim3(64 * COLSUM_WAVES), 0, st, dZ, B, s.K, G + s.ob3);
     e = gemm(mk(B, s.H, s.K, dZ, s.K, 1, P + s.oW3, 1, s.K, dH2, nullptr, H2, 0), bf16, st);
     if (e != hipSuccess) return e;
     // layer 2
     e = gemm(mk(s.H, s.H, B, H1, 1, s.H, dH2, s.H, 1, G + s.oW2, nullptr, nullptr, 0), bf16, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum, dim3((s.H + 255) / 256), dim3(256), 0, st, dH2, B, s.H, G + s.ob2);
+    hipLaunchKernelGGL(colsum, dim3((s.H + 63) / 64), dim3(64 * COLSUM_WAVES), 0, st, dH2, B, s.H, G + s.ob2);
     e = gemm(mk(B, s.H, s.H, dH2, s.H, 1, P + s.oW2, 1, s.H, dH1, nullptr, H1, 0), bf16, st);
     if (e != hipSuccess) return e;
     // layer 1
     e = gemm(mk(s.d, s.H, B, X, 1, s.d, dH1, s.H, 1, G + s.oW1, nullptr, nullptr, 0, nullptr, idx),
              bf16, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum, dim3((s.H + 255) / 256), dim3(256), 0, st, dH1, B, s.H, G + s.ob1);
+    hipLaunchKernelGGL(colsum, dim3((s.H + 63) / 64), dim3(64 * COLSUM_WAVES), 0, st, dH1, B, s.H, G + s.ob1);
     return hipGetLastError();
 }
 
