@@ -118,9 +118,83 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g)
     }
 }
 
-hipError_t gemm(const GemmArgs &g, bool bf16, hipStream_t st)
+// Batch-deep products with few output tiles (the weight gradients): each of
+// the GEMM_SPLIT waves of a workgroup accumulates one contiguous k range of the
+// tile, and wave 0 adds the shares in wave order (a fixed order) before the
+// same epilogue as gemm_kernel.
+constexpr int GEMM_SPLIT = 8;
+
+template <bool BF16>
+__global__ __launch_bounds__(64 * GEMM_SPLIT) void gemm_splitk_kernel(GemmArgs g)
+{
+    __shared__ float part[GEMM_SPLIT - 1][16][64];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int tilesN = (g.N + 31) / 32;
+    const int ti = blockIdx.x / tilesN, tj = blockIdx.x % tilesN;
+    const int i0 = ti * 32, j0 = tj * 32;
+    const int ia = i0 + (lane & 31), jb = j0 + (lane & 31);
+    const bool iok = ia < g.M, jok = jb < g.N;
+    constexpr int KS = BF16 ? 16 : 2;  // k per matrix instruction
+    const int per = ((g.K + KS - 1) / KS + GEMM_SPLIT - 1) / GEMM_SPLIT * KS;
+    const int kbeg = w * per, kend = (w + 1) * per < g.K ? (w + 1) * per : g.K;
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    if (BF16) {
+        for (int k0 = kbeg; k0 < kend; k0 += 16) {
+            bf16x8 av, bv;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = k0 + (lane >> 5) * 8 + t;
+                const bool kok = k < kend;
+                av[t] = to_bf16(iok && kok ? g.A[aidx(g, ia, k)] : 0.f);
+                bv[t] = to_bf16(jok && kok ? g.B[k * g.bs0 + jb * g.bs1] : 0.f);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    } else {
+        for (int k0 = kbeg; k0 < kend; k0 += 2) {
+            const int k = k0 + (lane >> 5);
+            const bool kok = k < kend;
+            const float av = iok && kok ? g.A[aidx(g, ia, k)] : 0.f;
+            const float bv = jok && kok ? g.B[k * g.bs0 + jb * g.bs1] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part[w - 1][r][lane] = acc[r];
+    }
+    __syncthreads();
+    if (w != 0) return;
+    for (int q = 0; q < GEMM_SPLIT - 1; ++q) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] += part[q][r][lane];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + (lane & 31);
+        if (i < g.M && j < g.N) {
+            float v = acc[r];
+            if (g.bias) v = v + g.bias[j];
+            if (g.relu) v = v > 0.f ? v : 0.f;
+            if (g.mask && !(g.mask[(int64_t)i * g.N + j] > 0.f)) v = 0.f;
+            g.C[(int64_t)i * g.N + j] = v;
+        }
+    }
+}
+
+// splitk: a batch-deep product (weight gradient); with fewer than 128 output
+// tiles its k range is shared by the waves of a workgroup
+hipError_t gemm(const GemmArgs &g, bool bf16, hipStream_t st, bool splitk = false)
 {
     const unsigned tiles = (unsigned)(((g.M + 31) / 32) * ((g.N + 31) / 32));
+    if (splitk && tiles < 128) {
+        if (bf16) hipLaunchKernelGGL(gemm_splitk_kernel<true>, dim3(tiles), dim3(64 * GEMM_SPLIT), 0, st, g);
+        else hipLaunchKernelGGL(gemm_splitk_kernel<false>, dim3(tiles), dim3(64 * GEMM_SPLIT), 0, st, g);
+        return hipGetLastError();
+    }
     if (bf16) hipLaunchKernelGGL(gemm_kernel<true>, dim3(tiles), dim3(64), 0, st, g);
     else hipLaunchKernelGGL(gemm_kernel<false>, dim3(tiles), dim3(64), 0, st, g);
     return hipGetLastError();
@@ -377,20 +451,20 @@ hipError_t mlp_gradients(const MlpShape &s, const float *P, const float *X, cons
     hipLaunchKernelGGL(softmax_xent, dim3((B + 3) / 4), dim3(256), 0, st, Z, lab, idx, B, s.K, dZ, loss);
     if (loss_mean) hipLaunchKernelGGL(mean_of, dim3(1), dim3(256), 0, st, loss, B, loss_mean);
     // layer 3: dW3 = H2^T dZ, db3 = colsum dZ, dH2 = (dZ W3^T) * (H2 > 0)
-    e = gemm(mk(s.H, s.K, B, H2, 1, s.H, dZ, s.K, 1, G + s.oW3, nullptr, nullptr, 0), bf16, st);
+    e = gemm(mk(s.H, s.K, B, H2, 1, s.H, dZ, s.K, 1, G + s.oW3, nullptr, nullptr, 0), bf16, st, true);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(colsum, dim3((s.K + 63) / 64), dim3(64 * COLSUM_WAVES), 0, st, dZ, B, s.K, G + s.ob3);
     e = gemm(mk(B, s.H, s.K, dZ, s.K, 1, P + s.oW3, 1, s.K, dH2, nullptr, H2, 0), bf16, st);
     if (e != hipSuccess) return e;
     // layer 2
-    e = gemm(mk(s.H, s.H, B, H1, 1, s.H, dH2, s.H, 1, G + s.oW2, nullptr, nullptr, 0), bf16, st);
+    e = gemm(mk(s.H, s.H, B, H1, 1, s.H, dH2, s.H, 1, G + s.oW2, nullptr, nullptr, 0), bf16, st, true);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(colsum, dim3((s.H + 63) / 64), dim3(64 * COLSUM_WAVES), 0, st, dH2, B, s.H, G + s.ob2);
     e = gemm(mk(B, s.H, s.H, dH2, s.H, 1, P + s.oW2, 1, s.H, dH1, nullptr, H1, 0), bf16, st);
     if (e != hipSuccess) return e;
     // layer 1
     e = gemm(mk(s.d, s.H, B, X, 1, s.d, dH1, s.H, 1, G + s.oW1, nullptr, nullptr, 0, nullptr, idx),
-             bf16, st);
+             bf16, st, true);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(colsum, dim3((s.H + 63) / 64), dim3(64 * COLSUM_WAVES), 0, st, dH1, B, s.H, G + s.ob1);
     return hipGetLastError();
