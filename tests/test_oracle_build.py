@@ -251,3 +251,19 @@ def test_threads_do_not_change_results():
     assert e1 == e2 and (a1 == a2).all()
     for u, v in zip(r1, r2):
         assert (u == v).all()
+
+
+@pytest.mark.parametrize("mode", [oracle.FP32, oracle.FP64])
+def test_connect_hand_traced_cases(mode):
+    """Hand-traced rounds of the connectivity phase (Alg. 3 phase 4): which
+    unreached points are attached in a round (those without an in-edge from
+    the unreached set, else the smallest id), to which row (the first search
+    result with a free slot, else the nearest reached point with one), and in
+    what order competing points are applied."""
+    g = json.load(open(os.path.join(GOLD, "connect_cases.json")))
+    for c in g["cases"]:
+        adj, added, rounds = oracle.connect(np.array(c["points"], np.float32),
+                                            np.array(c["adj"], np.uint32), c["entry"], c["Lc"],
+                                            mode=mode)
+        assert adj.tolist() == c["expect_adj"], c["name"]
+        assert added == c["expect_added"] and rounds == c["expect_rounds"], c["name"]

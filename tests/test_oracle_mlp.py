@@ -67,3 +67,22 @@ def test_fresh_queries_share_the_distribution():
     assert not np.array_equal(t, t2)
     # same centres: the per-cluster means of the base set explain the new queries
     assert abs(np.linalg.norm(x.mean(0)) - np.linalg.norm(t.mean(0))) < 0.5
+
+
+def test_adam_second_step_closed_forms():
+    """Two bias-corrected steps, worked out by hand.  A constant gradient g
+    gives m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so every step moves by
+    lr * sign(g) (up to eps).  Gradients +1 then -1 give m_2 = -(1 - b1)^2 and
+    v_2 = 1 - b2^2, so the second step adds lr (1 - b1) / (1 + b1) (= lr / 19
+    at b1 = 0.9)."""
+    lr = 0.01
+    g = np.array([0.7, -3.0])
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    for t in (1, 2, 3):
+        p, m, v = mlp.adam_step(p, g, m, v, t, lr)
+        np.testing.assert_allclose(p, -t * lr * np.sign(g), rtol=1e-6)
+    p1, m, v = mlp.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, lr)
+    p2, m, v = mlp.adam_step(p1, -np.ones(1), m, v, 2, lr)
+    np.testing.assert_allclose(m, [-(0.1 ** 2)], rtol=1e-12)
+    np.testing.assert_allclose(v, [1 - 0.999 ** 2], rtol=1e-12)
+    np.testing.assert_allclose(p2, p1 + lr / 19, rtol=1e-7)

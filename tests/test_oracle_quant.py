@@ -93,3 +93,22 @@ def test_rerank_recovers_exact_distances():
         exact = [np.sqrt(np.float32(oracle.dist_f32(q[i], x[j]))) for j in ids[i]]
         assert np.array_equal(np.float32(exact), dists[i].astype(np.float32))
         assert (np.diff(dists[i]) >= 0).all()
+
+
+def test_rerank_hand_traced_whole_beam():
+    """The re-rank covers every entry of the final beam (not only its first
+    k) and nothing outside it: hand-traced in tests/golden/rerank_line.json."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rerank_line.json")))
+    sp = np.array(g["search_points"], np.float32)
+    rp = np.array(g["rerank_points"], np.float32)
+    adj = np.array(g["adj"], np.uint32)
+    q = np.array([g["query"]], np.float32)
+    for c in g["cases"]:
+        for mode in (oracle.FP32, oracle.FP64):
+            ids, dists, hops, ndc = oracle.search_rerank(sp, rp, adj, q, c["k"], g["L"], g["entry"],
+                                                         mode=mode)
+            assert ids[0].tolist() == c["expect_ids"]
+            assert dists[0].tolist() == c["expect_dists"]
+            assert hops[0] == 3 and ndc[0] == 4
