@@ -81,6 +81,14 @@ def lib():
         L.orc_search_rerank.argtypes = [f32p, C.c_void_p, i64, C.c_int, u32p, C.c_int, f32p, i64,
                                         C.c_int, C.c_int, u32p, i64, C.c_int, u32p, f64p,
                                         C.c_void_p, C.c_void_p]
+        L.orc_dot_f32.restype = C.c_float
+        L.orc_dot_f32.argtypes = [f32p, f32p, C.c_int]
+        L.orc_fp8_encode.argtypes = [f32p, i64, C.c_int, f32p, f32p, f32p]
+        L.orc_fp8_score.restype = C.c_float
+        L.orc_fp8_score.argtypes = [f32p, f32p, C.c_float, C.c_float, C.c_int]
+        L.orc_search_fp8.argtypes = [f32p, f32p, f32p, C.c_void_p, i64, C.c_int, u32p, C.c_int, f32p,
+                                     i64, C.c_int, C.c_int, u32p, i64, u32p, f64p, C.c_void_p,
+                                     C.c_void_p]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -114,6 +122,13 @@ def dist_f64(x, y) -> float:
     """The same reduction order in double precision."""
     x, y = _f32(x), _f32(y)
     return float(lib().orc_dist_f64(x, y, x.size))
+
+
+def dot_f32(x, y) -> np.float32:
+    """Fixed-order single precision dot product (the lanes and butterfly of
+    dist_f32)."""
+    x, y = _f32(x), _f32(y)
+    return np.float32(lib().orc_dot_f32(x, y, x.size))
 
 
 def knn(rows, cols, C: int, exclude_self: bool = False, mode: int = FP32):
@@ -276,4 +291,43 @@ def search_rerank(search_points, rerank_points, adj, queries, k: int, L: int, en
     _check(lib().orc_search_rerank(sp, rp.ctypes.data if rp is not None else None, n, d, adj,
                                    adj.shape[1], qs, nq, k, L, entries, entries.size, mode, ids,
                                    dists, hops.ctypes.data, ndc.ctypes.data), "search_rerank")
+    return ids, dists, hops, ndc
+
+
+def fp8_encode(points):
+    """fp8 form of the stored vectors -> (E4M3 values c [n, d] unscaled,
+    scales s [n], n2 [n] = fl(fl(s s) dot(c, c)))."""
+    points = _f32(points)
+    n, d = points.shape
+    c = np.empty_like(points)
+    sc = np.empty(n, np.float32)
+    n2 = np.empty(n, np.float32)
+    _check(lib().orc_fp8_encode(points, n, d, c, sc, n2), "fp8_encode")
+    return c, sc, n2
+
+
+def fp8_score(encoded, q, v: int) -> np.float32:
+    """fp8 dot-form score of stored vector v (from fp8_encode) against q."""
+    c, sc, n2 = encoded
+    q = _f32(q)
+    return np.float32(lib().orc_fp8_score(q, _f32(c[v]), float(sc[v]), float(n2[v]), q.size))
+
+
+def search_fp8(encoded, rerank_points, adj, queries, k: int, L: int, entries):
+    """Beam search scored by the fp8 dot form of ``encoded`` (from
+    fp8_encode); the final beam re-ranked with ``rerank_points`` (float32)."""
+    c, sc, n2 = (_f32(a) for a in encoded)
+    qs = _f32(queries)
+    rp = _f32(rerank_points) if rerank_points is not None else None
+    n, d = c.shape
+    adj = np.ascontiguousarray(adj, np.uint32)
+    entries = np.ascontiguousarray(np.atleast_1d(entries), np.uint32)
+    nq = qs.shape[0]
+    ids = np.empty((nq, k), np.uint32)
+    dists = np.empty((nq, k), np.float64)
+    hops = np.empty(nq, np.uint32)
+    ndc = np.empty(nq, np.uint32)
+    _check(lib().orc_search_fp8(c, sc, n2, rp.ctypes.data if rp is not None else None, n, d, adj,
+                                adj.shape[1], qs, nq, k, L, entries, entries.size, ids, dists,
+                                hops.ctypes.data, ndc.ctypes.data), "search_fp8")
     return ids, dists, hops, ndc

@@ -79,6 +79,25 @@ double orc_dist_f64(const float *x, const float *y, int d)
     return acc[0];
 }
 
+/* Fixed-order single-precision dot product: the lanes and butterfly of
+ * orc_dist_f32 with acc = fma(x_i, y_i, acc) (the precision form's fp8 score
+ * is built from it). */
+float orc_dot_f32(const float *x, const float *y, int d)
+{
+    float acc[32];
+    for (int l = 0; l < 32; ++l) acc[l] = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        int l = (i / 4) % 32;
+        acc[l] = fmaf(x[i], y[i], acc[l]);
+    }
+    for (int off = 16; off >= 1; off /= 2) {
+        float next[32];
+        for (int l = 0; l < 32; ++l) next[l] = acc[l] + acc[l ^ off];
+        for (int l = 0; l < 32; ++l) acc[l] = next[l];
+    }
+    return acc[0];
+}
+
 static double dist_mode(const float *x, const float *y, int d, int mode)
 {
     return mode == ORC_FP32 ? (double)orc_dist_f32(x, y, d) : orc_dist_f64(x, y, d);
@@ -451,6 +470,30 @@ uint32_t orc_medoid(const float *pts, int64_t n, int d)
 /* the first ORC_NONE or out-of-range id.  hops = |E|; ndc counts the distinct */
 /* points whose distance to q was evaluated (the entry included).              */
 /* ------------------------------------------------------------------------- */
+/* How a beam search scores a point v against the query q:
+ *   canonical: D(q, x_v) of the mode (pts = the vectors searched);
+ *   fp8 form (scales != NULL, float32): pts = the E4M3 values c_v (unscaled),
+ *   s_v = scales[v], n2_v = n2[v] = fl(fl(s_v s_v) dot(c_v, c_v)), and
+ *     D = fma(-2 s_v, dot(q, c_v), fl(dot(q, q) + n2_v)), clamped at +0,
+ *   the dot form of |q - s_v c_v|^2 with float32 accumulation. */
+typedef struct {
+    const float *pts;
+    const float *scales;
+    const float *n2;
+    int mode;
+} orc_scorer;
+
+static double score_point(const orc_scorer *sc, const float *q, float qq, uint32_t v, int d)
+{
+    const float *x = sc->pts + (size_t)v * d;
+    if (!sc->scales) return dist_mode(q, x, d, sc->mode);
+    const float s = sc->scales[v];
+    const float dot = orc_dot_f32(q, x, d);
+    const float base = qq + sc->n2[v];
+    const float D = fmaf(-2.0f * s, dot, base);
+    return D > 0.0f ? (double)D : 0.0;
+}
+
 typedef struct {
     double *D;
     uint32_t *id;
@@ -499,13 +542,14 @@ static void beam_clear_seen(orc_beam *b)
 }
 
 /* One query.  Returns the final Q size (<= Leff); Q is left in b. */
-static int beam_one(orc_beam *b, const float *pts, int64_t n, int d, const uint32_t *adj, int R,
-                    const float *q, uint32_t s, int Leff, int mode, uint32_t *hops, uint32_t *ndc,
+static int beam_one(orc_beam *b, const orc_scorer *sc, int64_t n, int d, const uint32_t *adj, int R,
+                    const float *q, uint32_t s, int Leff, uint32_t *hops, uint32_t *ndc,
                     uint32_t *trace, int trace_cap, int *trace_len)
 {
     int qn = 1, h = 0;
     uint32_t nd = 0;
-    b->D[0] = dist_mode(q, pts + (size_t)s * d, d, mode);
+    const float qq = sc->scales ? orc_dot_f32(q, q, d) : 0.0f;
+    b->D[0] = score_point(sc, q, qq, s, d);
     b->id[0] = s;
     b->expl[0] = 0;
     if (beam_mark_seen(b, s) > 0) ++nd;
@@ -523,7 +567,7 @@ static int beam_one(orc_beam *b, const float *pts, int64_t n, int d, const uint3
             for (int t = 0; t < qn; ++t)
                 if (b->id[t] == v) { inq = 1; break; }
             if (inq) continue; /* set union */
-            double Dv = dist_mode(q, pts + (size_t)v * d, d, mode);
+            double Dv = score_point(sc, q, qq, v, d);
             if (beam_mark_seen(b, v) > 0) ++nd;
             int pos = qn;
             while (pos > 0 && key_less(Dv, v, b->D[pos - 1], b->id[pos - 1])) {
@@ -574,8 +618,9 @@ int orc_search(const float *pts, int64_t n, int d, const uint32_t *adj, int R,
             if (!ok) continue;
             uint32_t s = entries[n_entries == 1 ? 0 : i];
             uint32_t h = 0, nd = 0;
-            int qn = beam_one(&b, pts, n, d, adj, R, queries + (size_t)i * d, s, Leff, mode, &h,
-                              &nd, NULL, 0, NULL);
+            const orc_scorer sc = {pts, NULL, NULL, mode};
+            int qn = beam_one(&b, &sc, n, d, adj, R, queries + (size_t)i * d, s, Leff, &h, &nd,
+                              NULL, 0, NULL);
             for (int j = 0; j < k; ++j) {
                 ids[(size_t)i * k + j] = j < qn ? b.id[j] : ORC_NONE;
                 dists[(size_t)i * k + j] = j < qn ? delta_mode(b.D[j], mode) : INFINITY;
@@ -597,7 +642,8 @@ int orc_search_trace(const float *pts, int64_t n, int d, const uint32_t *adj, in
     int Leff = L > k ? L : k;
     orc_beam b;
     if (!beam_init(&b, n, Leff + R + 1)) { beam_free(&b); return ORC_ENOMEM; }
-    int qn = beam_one(&b, pts, n, d, adj, R, q, entry, Leff, mode, NULL, NULL, trace, trace_cap,
+    const orc_scorer sc = {pts, NULL, NULL, mode};
+    int qn = beam_one(&b, &sc, n, d, adj, R, q, entry, Leff, NULL, NULL, trace, trace_cap,
                       trace_len);
     for (int j = 0; j < k; ++j) {
         ids[j] = j < qn ? b.id[j] : ORC_NONE;
@@ -672,13 +718,68 @@ int orc_dequantized(const float *pts, int64_t n, int d, int dtype, float *out, f
     return ORC_OK;
 }
 
-/* Beam search over `spts` (the stored, possibly reduced-precision vectors),
- * then, when rpts is given, the final beam (all of its L entries) is re-ranked
- * by distances to the float32 vectors rpts and the first k returned. */
+/* Beam search scored by `sc`, then, when rpts is given, the final beam (all
+ * of its L entries) is re-ranked by distances to the float32 vectors rpts and
+ * the first k returned. */
+static int search_scored(const orc_scorer *sc, const float *rpts, int64_t n, int d,
+                         const uint32_t *adj, int R, const float *queries, int64_t nq, int k, int L,
+                         const uint32_t *entries, int64_t n_entries, int mode, uint32_t *ids,
+                         double *dists, uint32_t *hops, uint32_t *ndc);
+
+/* Beam search over `spts` (the stored, possibly reduced-precision vectors, by
+ * the canonical distance), with the re-rank of search_scored. */
 int orc_search_rerank(const float *spts, const float *rpts, int64_t n, int d, const uint32_t *adj,
                       int R, const float *queries, int64_t nq, int k, int L,
                       const uint32_t *entries, int64_t n_entries, int mode, uint32_t *ids,
                       double *dists, uint32_t *hops, uint32_t *ndc)
+{
+    const orc_scorer sc = {spts, NULL, NULL, mode};
+    return search_scored(&sc, rpts, n, d, adj, R, queries, nq, k, L, entries, n_entries, mode, ids,
+                         dists, hops, ndc);
+}
+
+/* fp8 form of the stored vectors: per vector the scale s = max|x| / 448 (1
+ * for a zero vector), the E4M3 values c_i = e4m3(x_i / s) (unscaled) and
+ * n2 = fl(fl(s s) dot(c, c)) (fixed-order dot). */
+int orc_fp8_encode(const float *pts, int64_t n, int d, float *cvals, float *scales, float *n2)
+{
+    if (n < 0 || d < 1) return ORC_EINVAL;
+    for (int64_t p = 0; p < n; ++p) {
+        const float *x = pts + (size_t)p * d;
+        float *c = cvals + (size_t)p * d;
+        const float sc = orc_fp8_scale(x, d);
+        for (int i = 0; i < d; ++i) c[i] = orc_round_e4m3(x[i] / sc);
+        scales[p] = sc;
+        const float ss = sc * sc;
+        n2[p] = ss * orc_dot_f32(c, c, d);
+    }
+    return ORC_OK;
+}
+
+/* The fp8 score of one stored vector (c, s, n2) against q (see orc_scorer). */
+float orc_fp8_score(const float *q, const float *c, float s, float n2, int d)
+{
+    const orc_scorer sc = {c, &s, &n2, ORC_FP32};
+    return (float)score_point(&sc, q, orc_dot_f32(q, q, d), 0, d);
+}
+
+/* Beam search scored by the fp8 dot form (float32), the final beam re-ranked
+ * with the float32 vectors rpts. */
+int orc_search_fp8(const float *cvals, const float *scales, const float *n2, const float *rpts,
+                   int64_t n, int d, const uint32_t *adj, int R, const float *queries, int64_t nq,
+                   int k, int L, const uint32_t *entries, int64_t n_entries, uint32_t *ids,
+                   double *dists, uint32_t *hops, uint32_t *ndc)
+{
+    if (!scales || !n2) return ORC_EINVAL;
+    const orc_scorer sc = {cvals, scales, n2, ORC_FP32};
+    return search_scored(&sc, rpts, n, d, adj, R, queries, nq, k, L, entries, n_entries, ORC_FP32,
+                         ids, dists, hops, ndc);
+}
+
+static int search_scored(const orc_scorer *sc, const float *rpts, int64_t n, int d,
+                         const uint32_t *adj, int R, const float *queries, int64_t nq, int k, int L,
+                         const uint32_t *entries, int64_t n_entries, int mode, uint32_t *ids,
+                         double *dists, uint32_t *hops, uint32_t *ndc)
 {
     if (n < 1 || d < 1 || R < 1 || k < 1 || L < 1 || nq < 0) return ORC_EINVAL;
     if (n_entries != 1 && n_entries != nq) return ORC_EINVAL;
@@ -702,7 +803,7 @@ int orc_search_rerank(const float *spts, const float *rpts, int64_t n, int d, co
             const float *q = queries + (size_t)i * d;
             uint32_t s = entries[n_entries == 1 ? 0 : i];
             uint32_t h = 0, nd = 0;
-            int qn = beam_one(&b, spts, n, d, adj, R, q, s, Leff, mode, &h, &nd, NULL, 0, NULL);
+            int qn = beam_one(&b, sc, n, d, adj, R, q, s, Leff, &h, &nd, NULL, 0, NULL);
             for (int j = 0; j < qn; ++j) {
                 rk[j].id = b.id[j];
                 rk[j].D = rpts ? dist_mode(q, rpts + (size_t)b.id[j] * d, d, mode) : b.D[j];
@@ -809,8 +910,8 @@ int orc_connect(const float *pts, int64_t n, int d, uint32_t *adj, int R, uint32
                 if (!ok) continue;
                 uint32_t p = A[a];
                 const float *xp = pts + (size_t)p * d;
-                int qn = beam_one(&b, pts, n, d, adj, R, xp, entry, Lc, mode, NULL, NULL, NULL, 0,
-                                  NULL);
+                const orc_scorer sc = {pts, NULL, NULL, mode};
+                int qn = beam_one(&b, &sc, n, d, adj, R, xp, entry, Lc, NULL, NULL, NULL, 0, NULL);
                 uint32_t t = ORC_NONE;
                 for (int j = 0; j < qn; ++j)
                     if (deg[b.id[j]] < R) { t = b.id[j]; break; }

@@ -119,3 +119,37 @@ def test_fp32_within_1e5_of_fp64():
             D32 = float(oracle.dist_f32(a, b))
             D64 = oracle.dist_f64(a, b)
             assert abs(np.sqrt(D32) - np.sqrt(D64)) <= 1e-5 * np.sqrt(D64)
+
+
+def emulate_dot(x, y) -> Fraction:
+    """The fixed-order dot product with exact rationals and explicit rounding."""
+    acc = [Fraction(0)] * 32
+    for i in range(len(x)):
+        lane = (i // 4) % 32
+        acc[lane] = round_f32(Fraction(float(x[i])) * Fraction(float(y[i])) + acc[lane])
+    off = 16
+    while off >= 1:
+        acc = [round_f32(acc[l] + acc[l ^ off]) for l in range(32)]
+        off //= 2
+    return acc[0]
+
+
+@pytest.mark.parametrize("d", [1, 4, 5, 33, 128, 129, 300])
+def test_dot_matches_exact_rational_emulation(d):
+    g = np.random.default_rng(100 + d)
+    for trial in range(3):
+        x = (g.standard_normal(d) * 10 ** g.uniform(-3, 3)).astype(np.float32)
+        y = (g.standard_normal(d) * 10 ** g.uniform(-3, 3)).astype(np.float32)
+        assert Fraction(float(oracle.dot_f32(x, y))) == emulate_dot(x, y)
+
+
+def test_dot_order_hand_worked():
+    """Elements 0 and 4 go to lanes 0 and 1: with x = (1, 0, 0, 0, 2^-24, ...)
+    and y = x the lanes hold 1 and 2^-48 and the butterfly adds them once:
+    1 + 2^-48 rounds to 1.  Elements 0 and 1 share lane 0: fma(2^-12, 2^-12, 1)
+    also rounds to 1, exactly as a left-to-right sum would."""
+    x = np.zeros(8, np.float32)
+    x[0], x[4] = 1.0, 2.0 ** -24
+    assert oracle.dot_f32(x, x) == np.float32(1.0)
+    assert oracle.dot_f32(np.array([3.0, 0, 0, 0, 5.0], np.float32),
+                          np.array([2.0, 0, 0, 0, -1.0], np.float32)) == np.float32(1.0)

@@ -112,3 +112,75 @@ def test_rerank_hand_traced_whole_beam():
             assert ids[0].tolist() == c["expect_ids"]
             assert dists[0].tolist() == c["expect_dists"]
             assert hops[0] == 3 and ndc[0] == 4
+
+
+# ---------------------------------------------------------------- fp8 dot form of the score
+def _fp8_score(enc, q, v):
+    """The oracle's fp8 score, checked to be what its search ranks by (a
+    one-point search: the entry's row is empty)."""
+    s = float(oracle.fp8_score(enc, q, v))
+    adj = np.full((len(enc[0]), 1), oracle.NONE, np.uint32)
+    ids, dists, _, _ = oracle.search_fp8(enc, None, adj, np.asarray(q, np.float32)[None], 1, 1, v)
+    assert ids[0, 0] == v and dists[0, 0] == float(np.sqrt(np.float32(s)))
+    return s
+
+
+def test_fp8_encode_matches_dequantized_values():
+    x, _ = workloads.generate(1, n=300, nq=1)
+    x[5] = 0.0
+    c, sc, n2 = oracle.fp8_encode(x)
+    deq, sc2 = oracle.dequantized(x, oracle.FP8)
+    assert np.array_equal(sc, sc2)
+    assert np.array_equal((c * sc[:, None]).astype(np.float32), deq)
+    assert sc[5] == 1.0 and n2[5] == 0.0
+    # n2 = fl(fl(s s) dot(c, c)) with the fixed-order dot
+    for p in (0, 7, 299):
+        assert n2[p] == np.float32(np.float32(sc[p] * sc[p]) * oracle.dot_f32(c[p], c[p]))
+
+
+def test_fp8_score_is_squared_distance_when_exact():
+    """Scale a power of two, stored values exact in E4M3, small integer query:
+    every float32 step is exact, so the dot form equals |q - x|^2 exactly."""
+    x = np.array([[448.0, -224.0, 96.0, 0.0, 12.0, -3.0, 7.0, 1.0],
+                  [224.0, 112.0, -56.0, 28.0, 14.0, 0.0, -7.0, 3.5]], np.float32)
+    enc = oracle.fp8_encode(x)
+    assert enc[1].tolist() == [1.0, 0.5]
+    assert np.array_equal(enc[0] * enc[1][:, None], x)
+    q = np.array([5.0, -2.0, 9.0, 1.0, 0.0, 4.0, -6.0, 2.0], np.float32)
+    for v in (0, 1):
+        want = float(((q.astype(np.float64) - x[v]) ** 2).sum())
+        assert _fp8_score(enc, q, v) == want
+
+
+def test_fp8_score_error_bound_and_clamp():
+    """Against |q - s c|^2 in float64 the dot form errs by at most
+    gamma_{d+4} (|q|^2 + 2 s |q.c| + s^2 |c|^2) (float32 accumulation and the
+    three combining steps); it never goes below zero, also for a query equal
+    to a stored vector, where the exact value is 0."""
+    x, q = workloads.generate(1, n=50, nq=20)
+    c, sc, n2 = enc = oracle.fp8_encode(x)
+    d = x.shape[1]
+    u = 2.0 ** -24
+    gam = (d + 4) * u / (1 - (d + 4) * u)
+    deq = (c * sc[:, None]).astype(np.float64)
+    for i in range(20):
+        for v in range(0, 50, 7):
+            exact = float(((q[i].astype(np.float64) - deq[v]) ** 2).sum())
+            mag = float((q[i].astype(np.float64) ** 2).sum() + 2 * sc[v] * np.abs(q[i] @ c[v]).sum() +
+                        sc[v] ** 2 * (c[v].astype(np.float64) ** 2).sum())
+            assert abs(_fp8_score(enc, q[i], v) - exact) <= gam * mag
+    for v in range(50):
+        s0 = _fp8_score(enc, deq[v].astype(np.float32), v)
+        assert 0.0 <= s0 <= gam * 4 * float((deq[v] ** 2).sum())
+
+
+def test_fp8_search_large_beam_is_exact_knn():
+    """A beam as large as the reachable set explores everything; the float32
+    re-rank of the whole beam then returns the exact k nearest neighbours."""
+    x, q = workloads.generate(1, n=600, nq=15)
+    adj, e, _ = oracle.build(x, 10, 20, 1.2)
+    assert oracle.reachable(adj, e).all()
+    ids, dists, hops, ndc = oracle.search_fp8(oracle.fp8_encode(x), x, adj, q, 10, 600, e)
+    gt, gD = oracle.knn(q, x, 10)
+    assert (ids == gt).all() and (hops == 600).all()
+    assert np.array_equal(dists, np.sqrt(gD.astype(np.float32)).astype(np.float64))
