@@ -36,7 +36,8 @@ BF16_MFMA_TFLOPS = 2500.0
 # elementwise kernel of known size gives), in bytes per launch, keyed by workload
 # and beam width.  Valid only while the search kernel's sources hash to `src`.
 SEARCH_TRAFFIC = {("sift_like_1m", 80): dict(bytes=10.267e9, src="d240e178f0dcc5bc")}
-KERNEL_SOURCES = ("paper_2510_05975_amd/csrc/search.hip", "paper_2510_05975_amd/csrc/common.hpp")
+KERNEL_SOURCES = ("paper_2510_05975_amd/csrc/search.hip", "paper_2510_05975_amd/csrc/beam.hpp",
+                  "paper_2510_05975_amd/csrc/common.hpp")
 
 
 def search_traffic(workload, L):
@@ -368,7 +369,7 @@ def quant_form(cng, torch, x, q, xd, qd, g, dtype, gt_ids, gt_dk, k, Ls, fp32_by
     L = row["L"]
     ms = timed(torch, lambda: cng.search_quantized(xd, st, g.adj, qd, k, L, g.entry), reps)
     b = 2 if dtype == cng.BF16 else 1
-    bytes_q = row["ndc"] * (d * b + (4 if dtype == cng.FP8 else 0)) + row["hops"] * W * 4 + \
+    bytes_q = row["ndc"] * (d * b + (8 if dtype == cng.FP8 else 0)) + row["hops"] * W * 4 + \
         max(L, k) * d * 4 + d * 4 + k * 8
     achieved = bytes_q * nq / (ms / 1e3) / 1e9
     # distance error of the returned (float32 re-ranked) distances against float64
@@ -563,7 +564,7 @@ def learned_form(cng, torch, a, cfg_id, prepared):
     train_s = time.perf_counter() - t0
     # held-out accuracy of the label and the gate threshold on validation queries
     vlab = Lb.entry_labels(xd, g.adj, g.entry, vad, 64, ents)
-    Z = Lb.mlp_logits(model.params, d, H, K, vad, 1)
+    Z = model.logits(vad)
     acc = float((Z.argmax(1).int() == vlab).float().mean())
     st16 = cng.quantize(xd, cng.BF16)
     torch.cuda.synchronize()

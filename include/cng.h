@@ -66,6 +66,9 @@ typedef struct {
     int32_t visited_log2;/* log2 of the search visited-table slots (0 = automatic) */
     double alpha_max;    /* adaptive alpha (Algorithm 4): largest alpha tried, >= alpha */
     double alpha_step;   /* adaptive alpha step; 0 = fixed alpha (Algorithm 2 alone) */
+    int32_t pass_rows;   /* rows per pass of the candidate filter, >= 0 (0 = sized from a band
+                            memory budget); rounded up to whole workgroups of 256 rows.  Only
+                            splits the work: candidate lists do not depend on it */
 } cng_build_params;
 
 typedef struct {
@@ -110,15 +113,17 @@ cng_status cng_entry_point(const float *points, int64_t n, int32_t d, uint32_t *
 /* Stage: exact candidate lists.  For every row r of `rows` [nr x d], the C
  * columns of `cols` [nc x d] nearest by (D, id), ascending; with exclude_self
  * (requires rows == cols, nr == nc) column r is skipped for row r.  Missing
- * entries (C > available columns) are CNG_NONE / +inf.
+ * entries (C > available columns) are CNG_NONE / +inf.  band: per-row capacity
+ * of the filter (0 = automatic, as in cng_build_params); pass_rows: rows per
+ * filter pass (0 = automatic), results do not depend on it.
  *   ids [nr x C] uint32, D [nr x C] float32 squared distances (fixed order).
  * Replaces the approximate K-NN graph + beam-search candidates of Algorithm 3
  * (phases 1-2) by the exact C nearest neighbours. */
 cng_status cng_knn_workspace_size(int64_t nr, int64_t nc, int32_t d, int32_t C, int32_t band,
-                                  size_t *bytes_host);
+                                  int64_t pass_rows, size_t *bytes_host);
 cng_status cng_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int32_t d,
-                   int32_t C, int32_t exclude_self, int32_t band, uint32_t *ids, float *D,
-                   void *workspace, size_t workspace_bytes, void *stream,
+                   int32_t C, int32_t exclude_self, int32_t band, int64_t pass_rows, uint32_t *ids,
+                   float *D, void *workspace, size_t workspace_bytes, void *stream,
                    int64_t *overflow_rows_host);
 
 /* Stage: pruning (Algorithm 2 with Eq. (1), fixed alpha, at most R kept).
@@ -210,20 +215,26 @@ size_t cng_quantized_bytes(int64_t n, int32_t d, int32_t dtype);
 
 /* Reduced-precision copy of points [n x d] float32 for scoring in the search.
  *   CNG_BF16:     vecs [n x d] uint16 bf16 bits, each element rounded to nearest even.
- *   CNG_FP8_E4M3: vecs [n x d] uint8 codes and scales [n] float32; per vector
- *                 s = max|x| / 448 (1 if the vector is zero), code = E4M3 value
- *                 nearest x / s (ties to even, saturating at +-448); an element
- *                 stands for value(code) * s.
+ *   CNG_FP8_E4M3: vecs [n x d] uint8 codes and scales [n x 2] float32 pairs
+ *                 (s, n2); per vector s = max|x| / 448 (1 if the vector is
+ *                 zero), code = E4M3 value nearest x / s (ties to even,
+ *                 saturating at +-448), an element stands for value(code) * s;
+ *                 n2 = fl(fl(s s) dot(c, c)) with c the E4M3 values and dot the
+ *                 fixed-order dot product (the distance's lanes and butterfly,
+ *                 fused multiply-adds of products).
  * Finite inputs; enqueues and returns. */
 cng_status cng_quantize(const float *points, int64_t n, int32_t d, int32_t dtype, void *vecs,
                         float *scales, void *stream);
 
-/* Beam search (Algorithm 1) scoring the stored copy `vecs` (dtype as above,
- * widened to float32 values, same fixed reduction order), then the converged
- * beam of L_eff entries is re-ranked with float32 distances to `points` and
- * the first k are returned: ids and dists are the float32-exact values for the
- * returned points.  hops/ndc count the reduced-precision search only.  Other
- * arguments as cng_search.  dtype CNG_F32 (vecs == points) is plain search. */
+/* Beam search (Algorithm 1) scoring the stored copy `vecs` (dtype as above),
+ * then the converged beam of L_eff entries is re-ranked with float32
+ * distances to `points` and the first k are returned: ids and dists are the
+ * float32-exact values for the returned points.  bf16: the fixed-order
+ * squared distance of the widened values.  fp8 (scales = the (s, n2) pairs of
+ * cng_quantize): the dot form D = fma(-2 s, dot(q, c), fl(dot(q, q) + n2)),
+ * clamped at +0, with float32 accumulation.  hops/ndc count the
+ * reduced-precision search only.  Other arguments as cng_search.  dtype
+ * CNG_F32 (vecs == points) is plain search. */
 cng_status cng_search_quantized(const float *points, const void *vecs, int32_t dtype,
                                 const float *scales, int64_t n, int32_t d, const uint32_t *adj,
                                 int32_t W, const float *queries, int64_t nq, int32_t k, int32_t L,
@@ -265,31 +276,55 @@ cng_status cng_entry_labels(const float *points, int64_t n, int32_t d, const uin
 int64_t cng_mlp_param_count(int32_t d, int32_t H, int32_t K);
 size_t cng_mlp_workspace_size(int32_t d, int32_t H, int32_t K, int32_t B);
 
+/* Input standardisation of the network.  The calls below that take x_mean
+ * [d] and x_scale [1] (device floats; both NULL: raw inputs) feed the first
+ * layer with (x - x_mean) / x_scale, computed in float32 per element.
+ * cng_mlp_input_stats gives the training set's statistics: x_mean = the
+ * column means (float64 sums over blocks of 4096 rows in order, then over the
+ * blocks), x_scale = the root-mean-square deviation from x_mean over all
+ * n * d elements (float64, at least 1e-12). */
+size_t cng_mlp_input_stats_workspace_size(int64_t n, int32_t d);
+cng_status cng_mlp_input_stats(const float *X, int64_t n, int32_t d, float *x_mean, float *x_scale,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
 /* Softmax cross-entropy gradients of a batch: rows batch_ids[0..B) of X
  * [* x d] (batch_ids may be NULL: rows 0..B-1) with labels[row] in [0, K).
- * grads [param_count]; loss (device float, may be NULL) = mean loss. */
+ * grads [param_count]; loss (device float, may be NULL) = mean loss.
+ * precision 1: every matrix product rounds both operands to bf16 (nearest
+ * even) and accumulates in float32; 0: float32 operands.  On return the
+ * workspace begins with the step's float32 intermediates, in this order:
+ * H1 [B x H], H2 [B x H] (hidden activations after ReLU), dH2 [B x H],
+ * dH1 [B x H] (their gradients, masked by the ReLU), Z [B x K] (logits),
+ * dZ [B x K] (softmax minus one-hot, over B), loss [B]. */
 cng_status cng_mlp_gradients(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
-                             const uint32_t *labels, const uint32_t *batch_ids, int32_t B,
-                             int32_t precision, float *grads, float *loss, void *workspace,
-                             size_t workspace_bytes, void *stream);
+                             const float *x_mean, const float *x_scale, const uint32_t *labels,
+                             const uint32_t *batch_ids, int32_t B, int32_t precision, float *grads,
+                             float *loss, void *workspace, size_t workspace_bytes, void *stream);
 
 /* One Adam step (bias-corrected, step >= 1) on params with moments m1, m2. */
 cng_status cng_mlp_adam(float *params, const float *grads, float *m1, float *m2, int32_t d,
                         int32_t H, int32_t K, int32_t step, float lr, float beta1, float beta2,
                         float eps, void *stream);
 
-/* Scores: logits [B x K] for X [B x d]. */
+/* Scores: logits [B x K] for X [B x d], computed as cng_entry_predict
+ * computes them (precision 1: the standardised input, the weights and each
+ * hidden activation after its ReLU are rounded to bf16, products accumulate
+ * in float32, biases are added in float32).  hidden (may be NULL):
+ * [2 x B x H] float32, the two hidden layers' activations as the following
+ * products read them (bf16 values in precision 1). */
 cng_status cng_mlp_logits(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
-                          int32_t B, int32_t precision, float *logits, void *workspace,
-                          size_t workspace_bytes, void *stream);
+                          const float *x_mean, const float *x_scale, int32_t B, int32_t precision,
+                          float *logits, float *hidden, void *workspace, size_t workspace_bytes,
+                          void *stream);
 
 /* Entry choice per query: entries[argmax] (ties to the lower index) if its
  * softmax probability is >= theta, else `fallback`.  out_entry [B] uint32,
  * out_conf [B] float (may be NULL). */
 cng_status cng_entry_predict(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
-                             int32_t B, int32_t precision, const uint32_t *entries,
-                             uint32_t fallback, float theta, uint32_t *out_entry, float *out_conf,
-                             void *workspace, size_t workspace_bytes, void *stream);
+                             const float *x_mean, const float *x_scale, int32_t B, int32_t precision,
+                             const uint32_t *entries, uint32_t fallback, float theta,
+                             uint32_t *out_entry, float *out_conf, void *workspace,
+                             size_t workspace_bytes, void *stream);
 
 /* Ablation baseline without a network: entries[index of the nearest centre]. */
 size_t cng_nearest_centre_workspace_size(int64_t nq, int32_t d, int32_t K);
@@ -303,32 +338,54 @@ cng_status cng_nearest_centre_entry(const float *queries, int64_t nq, int32_t d,
  * each wavefront repeatedly takes the next queued query (in submission
  * order), runs the beam search of cng_search / cng_search_quantized with that
  * query's k and L, and publishes the result.  Requests submitted while others
- * run join the same grid as ring slots free up.  One ring slot holds one
- * query (vector and results), so `capacity` slots bound the queries in flight
- * and their memory: cng_serve_submit refuses (CNG_ECAPACITY) a request whose
- * queries do not all fit in the next free slots; poll completed requests and
- * retry.  Results of a query do not depend on what else is in flight.
- * Rings and results live in coherent pinned host memory.  The grid ends on
- * cng_serve_stop, or by itself after several seconds without work (a later
- * poll then reports CNG_EDEVICE).  A server is used from one host thread. */
+ * run join the same grid as memory frees up.
+ *
+ * Admission is by footprint.  A request of nq queries with k results each
+ * holds nq * (4 d + 8 k) bytes (rounded up to 64) of a pinned arena while it
+ * is in flight (its query vectors and its result space) plus nq positions of
+ * the item ring; it is admitted into the first free range of the arena that
+ * holds it, wherever that is, so an earlier request that is still in flight
+ * blocks only its own bytes.  cng_serve_submit refuses (CNG_ECAPACITY) a
+ * request that does not fit now; poll completed requests and retry.  Each
+ * query's beam (max(L, k) <= 256 keys) and visited table live in the LDS of
+ * the wave that runs it.  Results of a query do not depend on what else is
+ * in flight.
+ *
+ * The grid leaves by itself after `idle_checks` empty polls (default 2^21,
+ * some seconds); the next submit or poll launches a fresh grid that resumes
+ * at the oldest incomplete item.  A server is used from one host thread. */
 typedef struct cng_server cng_server;
 
 typedef struct {
     const float *points;    /* [n x d] float32 (re-rank / plain scoring) */
     const void *vecs;       /* stored vectors scored by the search (== points for CNG_F32) */
     int32_t dtype;          /* cng_dtype of vecs */
-    const float *scales;    /* fp8 scales or NULL */
+    const float *scales;    /* fp8 (s, n2) pairs of cng_quantize, or NULL */
     int64_t n;
     int32_t d;              /* 4..512, multiple of 4 */
     const uint32_t *adj;    /* [n x W] */
     int32_t W;
     uint32_t entry;         /* default entry point */
     int32_t waves;          /* persistent wavefronts (0: 4 per compute unit) */
-    int32_t capacity;       /* ring slots = most queries in flight (0: 4 x waves) */
+    int32_t capacity;       /* item ring positions = most queries in flight (0: 16 x waves) */
     int32_t max_k;          /* largest k of any request, <= 256 */
     int32_t visited_log2;   /* 6..13; 0: the largest of 2^10 .. 2^13 slots whose
                                workgroups of 4 waves fit the LDS of a compute unit */
+    int64_t arena_bytes;    /* pinned bytes for the footprints of requests in flight
+                               (0: 4 x waves queries of 4 d + 8 max_k bytes); <= 16 GiB */
+    int32_t idle_checks;    /* empty polls after which the grid leaves (0: 2^21) */
 } cng_serve_config;
+
+typedef struct {
+    int64_t launches;       /* grids launched (1 + relaunches after an idle exit) */
+    int64_t submitted;      /* requests admitted */
+    int64_t completed;      /* requests retired by cng_serve_poll */
+    int64_t refused;        /* submits refused with CNG_ECAPACITY */
+    int64_t in_flight;      /* admitted, not yet retired */
+    int64_t arena_bytes;    /* arena size */
+    int64_t arena_used;     /* bytes held by requests in flight */
+    int32_t running;        /* 1 while a grid is on the device */
+} cng_serve_stats;
 
 /* Device workspace (bytes) the server keeps for its lifetime. */
 size_t cng_serve_workspace_size(void);
@@ -341,9 +398,11 @@ cng_status cng_serve_submit(cng_server *server, const float *queries_host, int32
                             int32_t L, const uint32_t *entries_host, uint64_t *req_host);
 /* done_host = 1 once every query of the request is complete; then ids_host /
  * dists_host [nq x k] (may be NULL) receive the results and the request is
- * retired.  done_host = 0 while pending. */
+ * retired (its footprint is free again).  done_host = 0 while pending. */
 cng_status cng_serve_poll(cng_server *server, uint64_t req, uint32_t *ids_host, float *dists_host,
                           int32_t *done_host);
+/* Counters of the server (host memory). */
+cng_status cng_serve_get_stats(cng_server *server, cng_serve_stats *stats_host);
 /* End the grid and release the server. */
 cng_status cng_serve_stop(cng_server *server);
 

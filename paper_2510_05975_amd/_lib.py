@@ -36,7 +36,8 @@ class CngError(RuntimeError):
 class BuildParams(C.Structure):
     _fields_ = [("R", C.c_int32), ("extra", C.c_int32), ("C", C.c_int32), ("alpha", C.c_double),
                 ("tau", C.c_double), ("flags", C.c_uint32), ("Lc", C.c_int32), ("band", C.c_int32),
-                ("visited_log2", C.c_int32), ("alpha_max", C.c_double), ("alpha_step", C.c_double)]
+                ("visited_log2", C.c_int32), ("alpha_max", C.c_double), ("alpha_step", C.c_double),
+                ("pass_rows", C.c_int32)]
 
 
 class BuildStats(C.Structure):
@@ -61,8 +62,8 @@ _SIGS = {
                             C.POINTER(BuildStats)]),
     "cng_entry_workspace_size": (sz, [i64, i32]),
     "cng_entry_point": (C.c_int, [vp, i64, i32, vp, vp, sz, vp]),
-    "cng_knn_workspace_size": (C.c_int, [i64, i64, i32, i32, i32, C.POINTER(sz)]),
-    "cng_knn": (C.c_int, [vp, i64, vp, i64, i32, i32, i32, i32, vp, vp, vp, sz, vp,
+    "cng_knn_workspace_size": (C.c_int, [i64, i64, i32, i32, i32, i64, C.POINTER(sz)]),
+    "cng_knn": (C.c_int, [vp, i64, vp, i64, i32, i32, i32, i32, i64, vp, vp, vp, sz, vp,
                           C.POINTER(i64)]),
     "cng_prune": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]),
     "cng_prune_adaptive": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double,
@@ -87,18 +88,22 @@ _SIGS = {
                                    vp]),
     "cng_mlp_param_count": (i64, [i32, i32, i32]),
     "cng_mlp_workspace_size": (sz, [i32, i32, i32, i32]),
-    "cng_mlp_gradients": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, sz, vp]),
+    "cng_mlp_input_stats_workspace_size": (sz, [i64, i32]),
+    "cng_mlp_input_stats": (C.c_int, [vp, i64, i32, vp, vp, vp, sz, vp]),
+    "cng_mlp_gradients": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, sz,
+                                    vp]),
     "cng_mlp_adam": (C.c_int, [vp, vp, vp, vp, i32, i32, i32, i32, C.c_float, C.c_float, C.c_float,
                                C.c_float, vp]),
-    "cng_mlp_logits": (C.c_int, [vp, i32, i32, i32, vp, i32, i32, vp, vp, sz, vp]),
-    "cng_entry_predict": (C.c_int, [vp, i32, i32, i32, vp, i32, i32, vp, u32, C.c_float, vp, vp,
-                                    vp, sz, vp]),
+    "cng_mlp_logits": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, sz, vp]),
+    "cng_entry_predict": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, i32, i32, vp, u32, C.c_float, vp,
+                                    vp, vp, sz, vp]),
     "cng_nearest_centre_workspace_size": (sz, [i64, i32, i32]),
     "cng_nearest_centre_entry": (C.c_int, [vp, i64, i32, vp, i32, vp, vp, vp, sz, vp]),
     "cng_serve_workspace_size": (sz, []),
     "cng_serve_start": (C.c_int, [C.c_void_p, vp, sz, C.POINTER(C.c_void_p)]),
     "cng_serve_submit": (C.c_int, [vp, vp, i32, i32, i32, vp, C.POINTER(C.c_uint64)]),
     "cng_serve_poll": (C.c_int, [vp, C.c_uint64, vp, vp, C.POINTER(i32)]),
+    "cng_serve_get_stats": (C.c_int, [vp, vp]),
     "cng_serve_stop": (C.c_int, [vp]),
 }
 
@@ -175,14 +180,15 @@ class Graph:
 def build(points: torch.Tensor, R: int, C_: int, alpha: float, tau: float = 0.0, extra: int = 1,
           connect: bool = True, Lc: int = 0, band: int = 0, visited_log2: int = 0,
           backward: bool = False, alpha_max: float | None = None,
-          alpha_step: float = 0.0) -> Graph:
+          alpha_step: float = 0.0, pass_rows: int = 0) -> Graph:
     """cng_build: entry point, exact candidates, pruning (adaptive alpha when
     alpha_step > 0), optional backward edges, connectivity."""
     x = _f32(points)
     n, d = x.shape
     flags = (BUILD_CONNECT if connect else 0) | (BUILD_BACKWARD if backward else 0)
     amax = alpha if alpha_max is None else alpha_max
-    p = BuildParams(R, extra, C_, alpha, tau, flags, Lc, band, visited_log2, amax, alpha_step)
+    p = BuildParams(R, extra, C_, alpha, tau, flags, Lc, band, visited_log2, amax, alpha_step,
+                    pass_rows)
     nb = sz(0)
     _check("cng_build_workspace_size", lib().cng_build_workspace_size(n, d, C.byref(p), C.byref(nb)))
     ws = _ws(nb.value, x.device)
@@ -204,13 +210,15 @@ def entry_point(points: torch.Tensor) -> int:
     return int(out.item()) & 0xFFFFFFFF
 
 
-def knn(rows: torch.Tensor, cols: torch.Tensor, C_: int, exclude_self: bool = False, band: int = 0):
+def knn(rows: torch.Tensor, cols: torch.Tensor, C_: int, exclude_self: bool = False, band: int = 0,
+        pass_rows: int = 0):
     """cng_knn -> (ids int32 [nr, C], D float32 [nr, C], overflow_rows)."""
     r, c = _f32(rows), _f32(cols)
     nr, d = r.shape
     nc = c.shape[0]
     nb = sz(0)
-    _check("cng_knn_workspace_size", lib().cng_knn_workspace_size(nr, nc, d, C_, band, C.byref(nb)))
+    _check("cng_knn_workspace_size", lib().cng_knn_workspace_size(nr, nc, d, C_, band, pass_rows,
+                                                                  C.byref(nb)))
     ws = _ws(nb.value, r.device)
     ids = torch.empty((nr, C_), dtype=torch.int32, device=r.device)
     D = torch.empty((nr, C_), dtype=torch.float32, device=r.device)
@@ -218,7 +226,7 @@ def knn(rows: torch.Tensor, cols: torch.Tensor, C_: int, exclude_self: bool = Fa
     same = exclude_self and rows.data_ptr() == cols.data_ptr()
     rp = _ptr(r)
     cp = rp if same else _ptr(c)
-    _check("cng_knn", lib().cng_knn(rp, nr, cp, nc, d, C_, int(exclude_self), band, _ptr(ids),
+    _check("cng_knn", lib().cng_knn(rp, nr, cp, nc, d, C_, int(exclude_self), band, pass_rows, _ptr(ids),
                                     _ptr(D), _ptr(ws), nb.value, _stream(), C.byref(ovf)))
     return ids, D, ovf.value
 
@@ -305,7 +313,7 @@ class Store:
     """Reduced-precision copy of the base vectors (cng_quantize)."""
     dtype: int
     vecs: torch.Tensor          # uint16 bf16 bits / uint8 fp8 codes, [n, d]
-    scales: torch.Tensor | None  # fp8 only, [n] float32
+    scales: torch.Tensor | None  # fp8 only, [n, 2] float32: scale s and n2 = s^2 |c|^2
 
 
 def quantize(points: torch.Tensor, dtype: int) -> Store:
@@ -316,7 +324,7 @@ def quantize(points: torch.Tensor, dtype: int) -> Store:
         scales = None
     elif dtype == FP8:
         vecs = torch.empty((n, d), dtype=torch.uint8, device=x.device)
-        scales = torch.empty(n, dtype=torch.float32, device=x.device)
+        scales = torch.empty((n, 2), dtype=torch.float32, device=x.device)
     else:
         raise ValueError("dtype must be BF16 or FP8")
     _check("cng_quantize", lib().cng_quantize(_ptr(x), n, d, dtype, _ptr(vecs), _ptr(scales),
@@ -380,13 +388,29 @@ def mlp_param_count(d: int, H: int, K: int) -> int:
     return int(lib().cng_mlp_param_count(d, H, K))
 
 
-def mlp_gradients(params, d, H, K, X, labels, batch_ids, B, precision, grads, loss=None, ws=None):
+def mlp_input_stats(X):
+    """cng_mlp_input_stats -> (x_mean [d], x_scale [1]) device float32."""
     X = _f32(X)
+    n, d = X.shape
+    nb = lib().cng_mlp_input_stats_workspace_size(n, d)
+    ws = _ws(nb, X.device)
+    mean = torch.empty(d, dtype=torch.float32, device=X.device)
+    scale = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check("cng_mlp_input_stats", lib().cng_mlp_input_stats(_ptr(X), n, d, _ptr(mean), _ptr(scale),
+                                                            _ptr(ws), nb, _stream()))
+    return mean, scale
+
+
+def mlp_gradients(params, d, H, K, X, labels, batch_ids, B, precision, grads, loss=None, ws=None,
+                  affine=None):
+    """affine: (x_mean, x_scale) device tensors, or None for raw inputs."""
+    X = _f32(X)
+    xm, xs = affine if affine is not None else (None, None)
     nb = lib().cng_mlp_workspace_size(d, H, K, B)
     if ws is None or ws.numel() < nb:
         ws = _ws(nb, X.device)
     _check("cng_mlp_gradients", lib().cng_mlp_gradients(
-        _ptr(params), d, H, K, _ptr(X), _ptr(_ids(labels)),
+        _ptr(params), d, H, K, _ptr(X), _ptr(xm), _ptr(xs), _ptr(_ids(labels)),
         _ptr(batch_ids) if batch_ids is not None else None, B, precision, _ptr(grads),
         _ptr(loss), _ptr(ws), ws.numel(), _stream()))
     return ws
@@ -397,25 +421,33 @@ def mlp_adam(params, grads, m1, m2, d, H, K, step, lr, beta1=0.9, beta2=0.999, e
                                               K, step, lr, beta1, beta2, eps, _stream()))
 
 
-def mlp_logits(params, d, H, K, X, precision):
+def mlp_logits(params, d, H, K, X, precision, affine=None, hidden=False):
+    """cng_mlp_logits -> Z [B, K] (and the hidden activations [2, B, H] with
+    ``hidden``)."""
     X = _f32(X)
+    xm, xs = affine if affine is not None else (None, None)
     B = X.shape[0]
     nb = lib().cng_mlp_workspace_size(d, H, K, B)
     ws = _ws(nb, X.device)
     Z = torch.empty((B, K), dtype=torch.float32, device=X.device)
-    _check("cng_mlp_logits", lib().cng_mlp_logits(_ptr(params), d, H, K, _ptr(X), B, precision,
-                                                  _ptr(Z), _ptr(ws), nb, _stream()))
-    return Z
+    Hd = torch.empty((2, B, H), dtype=torch.float32, device=X.device) if hidden else None
+    _check("cng_mlp_logits", lib().cng_mlp_logits(_ptr(params), d, H, K, _ptr(X), _ptr(xm), _ptr(xs),
+                                                  B, precision, _ptr(Z), _ptr(Hd), _ptr(ws), nb,
+                                                  _stream()))
+    return (Z, Hd) if hidden else Z
 
 
-def entry_predict(params, d, H, K, X, precision, entries, fallback: int, theta: float):
+def entry_predict(params, d, H, K, X, precision, entries, fallback: int, theta: float,
+                  affine=None):
     X = _f32(X)
+    xm, xs = affine if affine is not None else (None, None)
     B = X.shape[0]
     nb = lib().cng_mlp_workspace_size(d, H, K, B)
     ws = _ws(nb, X.device)
     out = torch.empty(B, dtype=torch.int32, device=X.device)
     conf = torch.empty(B, dtype=torch.float32, device=X.device)
-    _check("cng_entry_predict", lib().cng_entry_predict(_ptr(params), d, H, K, _ptr(X), B, precision,
+    _check("cng_entry_predict", lib().cng_entry_predict(_ptr(params), d, H, K, _ptr(X), _ptr(xm),
+                                                        _ptr(xs), B, precision,
                                                         _ptr(_ids(entries)), fallback, theta,
                                                         _ptr(out), _ptr(conf), _ptr(ws), nb,
                                                         _stream()))
@@ -439,7 +471,17 @@ class ServeConfig(C.Structure):
     _fields_ = [("points", C.c_void_p), ("vecs", C.c_void_p), ("dtype", C.c_int32),
                 ("scales", C.c_void_p), ("n", C.c_int64), ("d", C.c_int32), ("adj", C.c_void_p),
                 ("W", C.c_int32), ("entry", C.c_uint32), ("waves", C.c_int32),
-                ("capacity", C.c_int32), ("max_k", C.c_int32), ("visited_log2", C.c_int32)]
+                ("capacity", C.c_int32), ("max_k", C.c_int32), ("visited_log2", C.c_int32),
+                ("arena_bytes", C.c_int64), ("idle_checks", C.c_int32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("submitted", C.c_int64), ("completed", C.c_int64),
+                ("refused", C.c_int64), ("in_flight", C.c_int64), ("arena_bytes", C.c_int64),
+                ("arena_used", C.c_int64), ("running", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Server:
@@ -447,7 +489,8 @@ class Server:
     grid fed through pinned host rings.  Host arrays in, host arrays out."""
 
     def __init__(self, points: torch.Tensor, adj: torch.Tensor, entry: int, store: "Store | None" = None,
-                 max_k: int = 100, waves: int = 0, capacity: int = 0, visited_log2: int = 0):
+                 max_k: int = 100, waves: int = 0, capacity: int = 0, visited_log2: int = 0,
+                 arena_bytes: int = 0, idle_checks: int = 0):
         import numpy as np  # noqa: F401
         x = _f32(points)
         self._keep = [x, _ids(adj), store]
@@ -456,7 +499,7 @@ class Server:
                           store.dtype if store else F32,
                           store.scales.data_ptr() if (store and store.scales is not None) else None,
                           x.shape[0], self.d, _ids(adj).data_ptr(), adj.shape[1], entry, waves,
-                          capacity, max_k, visited_log2)
+                          capacity, max_k, visited_log2, arena_bytes, idle_checks)
         self._ws = _ws(lib().cng_serve_workspace_size(), x.device)
         torch.cuda.synchronize()
         h = C.c_void_p(0)
@@ -492,6 +535,11 @@ class Server:
             return None
         del self.pending[req]
         return ids, dists
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check("cng_serve_get_stats", lib().cng_serve_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
 
     def wait(self, req: int, timeout: float = 30.0):
         import time

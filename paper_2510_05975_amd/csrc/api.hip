@@ -108,7 +108,8 @@ cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSiz
     z->W = p->R + p->extra;
     z->Lc = p->Lc > 0 ? p->Lc : z->Ceff;
     if (z->Lc > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "Lc=%d exceeds %d", z->Lc, MAX_LEFF);
-    z->knn = cng::knn_plan(n, n, d, z->Ceff, p->band);
+    if (p->pass_rows < 0) return fail(CNG_EINVAL, "pass_rows=%d must be >= 0", p->pass_rows);
+    z->knn = cng::knn_plan(n, n, d, z->Ceff, p->band, p->pass_rows);
     z->cand_ids = align256((size_t)n * z->Ceff * 4);
     z->cand_D = align256((size_t)n * z->Ceff * 4);
     z->entry = align256(cng::entry_workspace_bytes(n, d));
@@ -240,31 +241,32 @@ cng_status cng_entry_point(const float *points, int64_t n, int32_t d, uint32_t *
 }
 
 cng_status cng_knn_workspace_size(int64_t nr, int64_t nc, int32_t d, int32_t C, int32_t band,
-                                  size_t *bytes)
+                                  int64_t pass_rows, size_t *bytes)
 {
     if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
     if (nr < 0 || nr > MAX_N || nc < 1 || nc > MAX_N) return fail(CNG_EINVAL, "nr/nc out of range");
     if (d < 1 || d > 4096) return fail(CNG_EINVAL, "d out of range");
     if (C < 1) return fail(CNG_EINVAL, "C must be >= 1");
     if (band < 0 || band > 2048) return fail(CNG_EUNSUPPORTED, "band must be in [0, 2048]");
+    if (pass_rows < 0) return fail(CNG_EINVAL, "pass_rows must be >= 0");
     int Ce = C;
     if (band == 0 && 2 * Ce + 128 > 512) return fail(CNG_EUNSUPPORTED, "C=%d exceeds 192", C);
-    *bytes = cng::knn_plan(nr, nc, d, Ce, band).bytes;
+    *bytes = cng::knn_plan(nr, nc, d, Ce, band, pass_rows).bytes;
     return ok();
 }
 
 cng_status cng_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int32_t d, int32_t C,
-                   int32_t exclude_self, int32_t band, uint32_t *ids, float *D, void *workspace,
-                   size_t ws_bytes, void *stream, int64_t *overflow_rows_host)
+                   int32_t exclude_self, int32_t band, int64_t pass_rows, uint32_t *ids, float *D,
+                   void *workspace, size_t ws_bytes, void *stream, int64_t *overflow_rows_host)
 {
     size_t need = 0;
-    cng_status s = cng_knn_workspace_size(nr, nc, d, C, band, &need);
+    cng_status s = cng_knn_workspace_size(nr, nc, d, C, band, pass_rows, &need);
     if (s != CNG_OK) return s;
     if (!rows || !cols || !ids || !D) return fail(CNG_EINVAL, "NULL array argument");
     if (exclude_self && (rows != cols || nr != nc)) return fail(CNG_EINVAL, "exclude_self needs rows == cols");
     if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     if (nr == 0) return ok();
-    cng::KnnPlan plan = cng::knn_plan(nr, nc, d, C, band);
+    cng::KnnPlan plan = cng::knn_plan(nr, nc, d, C, band, pass_rows);
     int64_t ovf = 0;
     int exact = 0, dtype = 0;
     hipError_t e = cng::launch_knn(rows, nr, cols, nc, d, C, exclude_self ? 1 : 0, plan, ids, D,
@@ -515,18 +517,46 @@ size_t cng_mlp_workspace_size(int32_t d, int32_t H, int32_t K, int32_t B)
     return cng::mlp_workspace_floats(cng::MlpShape(d, H, K), B) * 4;
 }
 
+static cng_status check_affine(const float *x_mean, const float *x_scale)
+{
+    if ((x_mean == nullptr) != (x_scale == nullptr))
+        return fail(CNG_EINVAL, "x_mean and x_scale must both be given or both be NULL");
+    return CNG_OK;
+}
+
+size_t cng_mlp_input_stats_workspace_size(int64_t n, int32_t d)
+{
+    if (n < 1 || d < 1) return 0;
+    return cng::mlp_stats_workspace_bytes(n, d);
+}
+
+cng_status cng_mlp_input_stats(const float *X, int64_t n, int32_t d, float *x_mean, float *x_scale,
+                               void *workspace, size_t ws_bytes, void *stream)
+{
+    cng_status s = check_points(X, n, d, 1);
+    if (s != CNG_OK) return s;
+    if (!x_mean || !x_scale) return fail(CNG_EINVAL, "NULL array argument");
+    if (!workspace || ws_bytes < cng::mlp_stats_workspace_bytes(n, d)) return fail(CNG_ENOMEM, "workspace too small");
+    hipError_t e = cng::mlp_input_stats(X, n, d, x_mean, x_scale, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp input stats");
+    return ok();
+}
+
 cng_status cng_mlp_gradients(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
-                             const uint32_t *labels, const uint32_t *batch_ids, int32_t B,
-                             int32_t precision, float *grads, float *loss, void *workspace,
-                             size_t ws_bytes, void *stream)
+                             const float *x_mean, const float *x_scale, const uint32_t *labels,
+                             const uint32_t *batch_ids, int32_t B, int32_t precision, float *grads,
+                             float *loss, void *workspace, size_t ws_bytes, void *stream)
 {
     cng_status s = check_mlp(d, H, K, B, precision);
+    if (s != CNG_OK) return s;
+    s = check_affine(x_mean, x_scale);
     if (s != CNG_OK) return s;
     if (!params || !X || !labels || !grads) return fail(CNG_EINVAL, "NULL array argument");
     cng::MlpShape sh(d, H, K);
     if (!workspace || ws_bytes < cng::mlp_workspace_floats(sh, B) * 4) return fail(CNG_ENOMEM, "workspace too small");
     hipError_t e = cng::mlp_gradients(sh, params, X, labels, batch_ids, B, precision == 1,
-                                      (float *)workspace, grads, loss, (hipStream_t)stream);
+                                      (float *)workspace, grads, loss, (hipStream_t)stream, x_mean,
+                                      x_scale);
     if (e != hipSuccess) return hip_fail(e, "mlp gradients");
     return ok();
 }
@@ -546,32 +576,39 @@ cng_status cng_mlp_adam(float *params, const float *grads, float *m1, float *m2,
 }
 
 cng_status cng_mlp_logits(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
-                          int32_t B, int32_t precision, float *logits, void *workspace,
-                          size_t ws_bytes, void *stream)
+                          const float *x_mean, const float *x_scale, int32_t B, int32_t precision,
+                          float *logits, float *hidden, void *workspace, size_t ws_bytes,
+                          void *stream)
 {
     cng_status s = check_mlp(d, H, K, B, precision);
+    if (s != CNG_OK) return s;
+    s = check_affine(x_mean, x_scale);
     if (s != CNG_OK) return s;
     if (!params || !X || !logits) return fail(CNG_EINVAL, "NULL array argument");
     cng::MlpShape sh(d, H, K);
     if (!workspace || ws_bytes < cng::mlp_workspace_floats(sh, B) * 4) return fail(CNG_ENOMEM, "workspace too small");
-    hipError_t e = cng::mlp_forward(sh, params, X, nullptr, B, precision == 1, (float *)workspace,
-                                    logits, (hipStream_t)stream);
+    hipError_t e = cng::mlp_scores(sh, params, X, B, precision == 1, (float *)workspace, logits,
+                                   (hipStream_t)stream, x_mean, x_scale, hidden);
     if (e != hipSuccess) return hip_fail(e, "mlp logits");
     return ok();
 }
 
 cng_status cng_entry_predict(const float *params, int32_t d, int32_t H, int32_t K, const float *X,
-                             int32_t B, int32_t precision, const uint32_t *entries,
-                             uint32_t fallback, float theta, uint32_t *out_entry, float *out_conf,
-                             void *workspace, size_t ws_bytes, void *stream)
+                             const float *x_mean, const float *x_scale, int32_t B, int32_t precision,
+                             const uint32_t *entries, uint32_t fallback, float theta,
+                             uint32_t *out_entry, float *out_conf, void *workspace, size_t ws_bytes,
+                             void *stream)
 {
     cng_status s = check_mlp(d, H, K, B, precision);
+    if (s != CNG_OK) return s;
+    s = check_affine(x_mean, x_scale);
     if (s != CNG_OK) return s;
     if (!params || !X || !entries || !out_entry) return fail(CNG_EINVAL, "NULL array argument");
     cng::MlpShape sh(d, H, K);
     if (!workspace || ws_bytes < cng::mlp_workspace_floats(sh, B) * 4) return fail(CNG_ENOMEM, "workspace too small");
     hipError_t e = cng::mlp_predict(sh, params, X, B, precision == 1, entries, fallback, theta,
-                                    (float *)workspace, out_entry, out_conf, (hipStream_t)stream);
+                                    (float *)workspace, out_entry, out_conf, (hipStream_t)stream,
+                                    x_mean, x_scale);
     if (e != hipSuccess) return hip_fail(e, "entry predict");
     return ok();
 }

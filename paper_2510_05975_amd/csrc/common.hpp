@@ -129,6 +129,27 @@ __device__ __forceinline__ double chunk_fma_f64(float4 a, float4 b, double acc)
     return acc;
 }
 
+// Partial sum of one lane for the fixed-order dot product: chunk r of lane gl
+// covers elements (r*32 + gl)*4 .. +3, acc = fma(a_i, b_i, acc) in order.
+__device__ __forceinline__ float chunk_dot(float4 a, float4 b, float acc)
+{
+    acc = __builtin_fmaf(a.x, b.x, acc);
+    acc = __builtin_fmaf(a.y, b.y, acc);
+    acc = __builtin_fmaf(a.z, b.z, acc);
+    acc = __builtin_fmaf(a.w, b.w, acc);
+    return acc;
+}
+
+// fp8 score from the fixed-order dot product of the query with the E4M3
+// values c of a stored vector, the query's squared norm qq (fixed order) and
+// the vector's scale s and n2 = fl(fl(s s) dot(c, c)):
+// fma(-2 s, dot, qq + n2), clamped at +0 (the dot form of |q - s c|^2).
+__device__ __forceinline__ float fp8_score(float dot, float qq, float s, float n2)
+{
+    const float D = __builtin_fmaf(-2.0f * s, dot, qq + n2);
+    return D > 0.0f ? D : 0.0f;
+}
+
 // Load chunk r of lane gl of a row (zeros past d).  VEC: d % 4 == 0 and rows
 // 16-byte aligned, so a chunk is one dwordx4 load.
 template <bool VEC>
@@ -190,12 +211,13 @@ __device__ __forceinline__ float e4m3_value(uint32_t c)
     return (c & 0x80u) ? -v : v;
 }
 
-// Chunk r of lane gl (elements (r*32 + gl)*4 .. +3) of a stored row, as the
-// float32 values it stands for.  ST 0: float32, 1: bf16, 2: fp8 (times scale).
-// VEC: d % 4 == 0 and the row base aligned to one chunk (one vector load).
+// Chunk r of lane gl (elements (r*32 + gl)*4 .. +3) of a stored row, as
+// float32 values.  ST 0: float32, 1: bf16, 2: fp8 E4M3 values (unscaled: the
+// fp8 score applies the scale after the dot product).  VEC: d % 4 == 0 and
+// the row base aligned to one chunk (one vector load).
 template <int ST, bool VEC>
 __device__ __forceinline__ float4 load_stored(const void *__restrict__ base, size_t row, int d, int r,
-                                              int gl, float scale)
+                                              int gl)
 {
     const int i = (r * 32 + gl) * 4;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -221,14 +243,14 @@ __device__ __forceinline__ float4 load_stored(const void *__restrict__ base, siz
         if (VEC) {
             if (i < d) {
                 const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
-                v = make_float4(e4m3_value(w & 0xFFu) * scale, e4m3_value((w >> 8) & 0xFFu) * scale,
-                                e4m3_value((w >> 16) & 0xFFu) * scale, e4m3_value(w >> 24) * scale);
+                v = make_float4(e4m3_value(w & 0xFFu), e4m3_value((w >> 8) & 0xFFu),
+                                e4m3_value((w >> 16) & 0xFFu), e4m3_value(w >> 24));
             }
         } else {
-            v.x = i + 0 < d ? e4m3_value(p[0]) * scale : 0.f;
-            v.y = i + 1 < d ? e4m3_value(p[1]) * scale : 0.f;
-            v.z = i + 2 < d ? e4m3_value(p[2]) * scale : 0.f;
-            v.w = i + 3 < d ? e4m3_value(p[3]) * scale : 0.f;
+            v.x = i + 0 < d ? e4m3_value(p[0]) : 0.f;
+            v.y = i + 1 < d ? e4m3_value(p[1]) : 0.f;
+            v.z = i + 2 < d ? e4m3_value(p[2]) : 0.f;
+            v.w = i + 3 < d ? e4m3_value(p[3]) : 0.f;
         }
         return v;
     }
@@ -254,20 +276,19 @@ __device__ __forceinline__ typename RawChunk<ST>::type load_raw(const void *__re
     return *reinterpret_cast<const T *>(reinterpret_cast<const uint8_t *>(base) + row * d + i);
 }
 
-__device__ __forceinline__ float4 decode_chunk(float4 w, float) { return w; }
-__device__ __forceinline__ float4 decode_chunk(uint2 w, float)
+__device__ __forceinline__ float4 decode_chunk(float4 w) { return w; }
+__device__ __forceinline__ float4 decode_chunk(uint2 w)
 {
     return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
                        __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
 }
 // fp8: the gfx950 conversion instruction widens two E4M3 codes per call
-// (exact); the product with the scale is one float32 rounding, as in the
-// element-wise definition above.
-__device__ __forceinline__ float4 decode_chunk(uint32_t w, float scale)
+// (exact E4M3 values, unscaled).
+__device__ __forceinline__ float4 decode_chunk(uint32_t w)
 {
     const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
     const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
-    return make_float4(lo[0] * scale, lo[1] * scale, hi[0] * scale, hi[1] * scale);
+    return make_float4(lo[0], lo[1], hi[0], hi[1]);
 }
 
 // Bitonic sort of n (power of two) 64-bit keys in LDS by one wavefront.

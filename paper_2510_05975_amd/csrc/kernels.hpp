@@ -36,25 +36,28 @@ struct ServeRing {
     uint64_t stop;  // non-zero: leave the loop
     uint64_t pad[6];
 };
-struct ServeItem {   // read by the device as four uint32 words
-    uint32_t req;    // request id (host bookkeeping)
-    uint32_t k, L;   // results wanted and beam width
-    uint32_t entry;  // entry point of the search
+struct ServeItem {   // read by the device as eight uint32 words
+    uint32_t tag_lo, tag_hi;  // the item number t this position holds
+    uint32_t k, L;            // results wanted and beam width
+    uint32_t entry;           // entry point of the search
+    uint32_t qoff;            // query vector: arena word offset (d floats)
+    uint32_t ioff, doff;      // result ids / distances: arena word offsets (k each)
 };
 struct ServeArgs {
     SearchArgs base;            // graph, vectors, storage, visited table size
     ServeRing *ring;
-    const ServeItem *items;     // [cap]
-    uint64_t cap;
-    const float *payload;       // [cap x d] query vectors
-    uint32_t *out_ids;          // [cap x max_k]
-    float *out_dists;           // [cap x max_k]
-    uint64_t *done;             // [cap]: t + 1 once item t is complete
+    const ServeItem *items;     // [rc] ring of item descriptors, item t at t % rc
+    uint64_t rc;
+    unsigned char *arena;       // query vectors and results of the requests in flight
+    uint64_t *done;             // [rc]: t + 1 once item t is complete
     unsigned long long *head;   // device memory: next item to claim
     uint64_t *mirror;           // device memory: [0] last tail seen, [1] stop seen
     uint32_t max_k;
     uint32_t idle_limit;
 };
+// head = first item to claim, mirror = {seen, 0}: before a (re)launch
+hipError_t launch_serve_reset(unsigned long long *head, uint64_t *mirror, uint64_t first,
+                              uint64_t seen, hipStream_t stream);
 hipError_t launch_serve(const ServeArgs &a, int waves, hipStream_t stream);
 size_t serve_lds_per_wave(int d, int vlog2);
 int search_default_vlog2(int Leff, int64_t nq, int store);
@@ -82,7 +85,9 @@ struct KnnPlan {
     int inner_band;
     size_t inner_bytes;
 };
-KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band);
+// pass_rows > 0 caps the rows of one filter pass (rounded to whole
+// workgroups); 0 sizes passes from the band memory budget
+KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band, int64_t pass_rows = 0);
 hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int d, int C,
                       int exclude_self, const KnnPlan &plan, uint32_t *ids, float *D, void *ws,
                       hipStream_t stream, int64_t *overflow_rows, int *exact_int, int *dtype);
@@ -116,16 +121,27 @@ struct MlpShape {
     MlpShape(int d_, int H_, int K_);
 };
 size_t mlp_workspace_floats(const MlpShape &s, int B);
+// mean [d] / scale [1] (device, both or neither): the network's input is
+// (x - mean) / scale, applied in float32 before the first layer
 hipError_t mlp_forward(const MlpShape &s, const float *P, const float *X, const uint32_t *idx, int B,
-                       bool bf16, float *ws, float *Z_out, hipStream_t st);
+                       bool bf16, float *ws, float *Z_out, hipStream_t st,
+                       const float *mean = nullptr, const float *scale = nullptr);
 hipError_t mlp_gradients(const MlpShape &s, const float *P, const float *X, const uint32_t *lab,
                          const uint32_t *idx, int B, bool bf16, float *ws, float *G,
-                         float *loss_mean, hipStream_t st);
+                         float *loss_mean, hipStream_t st, const float *mean = nullptr,
+                         const float *scale = nullptr);
 hipError_t mlp_adam(const MlpShape &s, float *P, const float *G, float *M1, float *M2, int step,
                     float lr, float b1, float b2, float eps, hipStream_t st);
+hipError_t mlp_scores(const MlpShape &s, const float *P, const float *X, int B, bool bf16,
+                      float *ws, float *Z, hipStream_t st, const float *mean = nullptr,
+                      const float *scale = nullptr, float *hidden = nullptr);
 hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B, bool bf16,
                        const uint32_t *entries, uint32_t fallback, float theta, float *ws,
-                       uint32_t *out, float *conf, hipStream_t st);
+                       uint32_t *out, float *conf, hipStream_t st, const float *mean = nullptr,
+                       const float *scale = nullptr);
+size_t mlp_stats_workspace_bytes(int64_t n, int d);
+hipError_t mlp_input_stats(const float *X, int64_t n, int d, float *mean, float *scale, void *ws,
+                           hipStream_t st);
 
 // k-means (entry nodes of the learned entry point)
 size_t kmeans_workspace_bytes(int64_t n, int d, int K);

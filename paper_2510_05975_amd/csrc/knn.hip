@@ -1355,7 +1355,7 @@ int order_cells(int64_t n)
     return (int)(K < 2 ? 2 : K > 8192 ? 8192 : K);
 }
 
-KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
+KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band, int64_t pass_rows)
 {
     KnnPlan p{};
     int CB = band > 0 ? next_pow2(band) : next_pow2(2 * C + (d > 128 ? BNW : BN));
@@ -1370,7 +1370,7 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band)
     const int64_t rows_pad = (nr + BM2 - 1) / BM2 * BM2;
     const size_t budget = (size_t)rows_pad * CB * 8 <= ((size_t)4 << 30) ? (size_t)4 << 30
                                                                           : (size_t)1 << 30;
-    int64_t chunk = (int64_t)(budget / ((size_t)CB * 8));
+    int64_t chunk = pass_rows > 0 ? pass_rows : (int64_t)(budget / ((size_t)CB * 8));
     chunk = chunk / BM * BM;
     if (chunk < BM) chunk = BM;
     int64_t nr_pad = (nr + BM - 1) / BM * BM;

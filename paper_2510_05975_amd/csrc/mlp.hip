@@ -268,6 +268,79 @@ __global__ __launch_bounds__(256) void mean_of(const float *__restrict__ x, int 
     if (threadIdx.x == 0) *out = (float)(part[0] / n);
 }
 
+// Input affine of the network: out[i * d + c] = (X[row(i) * d + c] - mean[c]) / scale
+// in float32 (row(i) = idx[i], or i without an index map).
+__global__ void standardize_rows(const float *__restrict__ X, const uint32_t *__restrict__ idx,
+                                 int B, int d, const float *__restrict__ mean,
+                                 const float *__restrict__ scale, float *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)B * d) return;
+    const int64_t i = t / d, c = t % d;
+    const int64_t r = idx ? (int64_t)idx[i] : i;
+    out[t] = (X[r * d + c] - mean[c]) / scale[0];
+}
+
+// Statistics of the training inputs: per-column sums of a block of STAT_ROWS
+// rows in float64 (rows in order), then the block sums in block order.
+constexpr int STAT_ROWS = 4096;
+__global__ __launch_bounds__(256) void column_block_sums(const float *__restrict__ X, int64_t n, int d,
+                                                         double *__restrict__ part)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * STAT_ROWS;
+    const int64_t r1 = r0 + STAT_ROWS < n ? r0 + STAT_ROWS : n;
+    for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        double s = 0.0;
+        for (int64_t r = r0; r < r1; ++r) s += (double)X[r * d + c];
+        part[(int64_t)blockIdx.x * d + c] = s;
+    }
+}
+
+__global__ void column_means(const double *__restrict__ part, int nb, int64_t n, int d,
+                             float *__restrict__ mean)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * d + c];
+    mean[c] = (float)(s / (double)n);
+}
+
+// Sum of squared deviations from the (float32) column means, per row block.
+__global__ __launch_bounds__(256) void block_sq_dev(const float *__restrict__ X, int64_t n, int d,
+                                                    const float *__restrict__ mean,
+                                                    double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int64_t r0 = (int64_t)blockIdx.x * STAT_ROWS;
+    const int64_t r1 = r0 + STAT_ROWS < n ? r0 + STAT_ROWS : n;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        const double m = (double)mean[c];
+        for (int64_t r = r0; r < r1; ++r) {
+            const double t = (double)X[r * d + c] - m;
+            s += t * t;
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void rms_scale(const double *__restrict__ part, int nb, int64_t n, int d,
+                          float *__restrict__ scale)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    const double r = sqrt(s / ((double)n * d));
+    scale[0] = r > 1e-12 ? (float)r : 1e-12f;
+}
+
 __global__ void adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                      float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
                      float c1, float c2)
@@ -294,6 +367,18 @@ __global__ void pack_bf16(const float *__restrict__ src, int64_t rows, int cols,
     if (t >= rows * cols) return;
     const int64_t r = t / cols, c = t % cols;
     out[t] = bf16_bits(src[r * s0 + c * s1]);
+}
+
+// out[i * d + c] = bf16((X[i * d + c] - mean[c]) / scale), or bf16(X) without
+// an input affine: the first layer's operand, rounded as gemm_kernel rounds it.
+__global__ void pack_inputs(const float *__restrict__ X, int64_t B, int d,
+                            const float *__restrict__ mean, const float *__restrict__ scale,
+                            uint16_t *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * d) return;
+    const float v = X[t];
+    out[t] = bf16_bits(mean ? (v - mean[t % d]) / scale[0] : v);
 }
 
 // C = A Bt^T + bias with A [M x K] and Bt [N x K] bf16 (K a multiple of 16):
@@ -403,8 +488,46 @@ MlpShape::MlpShape(int d_, int H_, int K_) : d(d_), H(H_), K(K_)
 
 static size_t mlp_base_floats(const MlpShape &s, int B)
 {
-    // H1, H2, Z, dZ, dH2, dH1, loss
-    return ((size_t)B * s.H * 4 + (size_t)B * s.K * 2 + (size_t)B + 64 + 3) / 4 * 4;
+    // H1, H2, Z, dZ, dH2, dH1, loss, then the standardized inputs [B x d]
+    return ((size_t)B * s.H * 4 + (size_t)B * s.K * 2 + (size_t)B + 64 + 3) / 4 * 4 +
+           ((size_t)B * s.d + 3) / 4 * 4;
+}
+
+static float *std_inputs(const MlpShape &s, float *ws, int B)
+{
+    return ws + ((size_t)B * s.H * 4 + (size_t)B * s.K * 2 + (size_t)B + 64 + 3) / 4 * 4;
+}
+
+size_t mlp_stats_workspace_bytes(int64_t n, int d)
+{
+    const int64_t nb = (n + STAT_ROWS - 1) / STAT_ROWS;
+    return (size_t)nb * d * 8 + (size_t)nb * 8 + 256;
+}
+
+hipError_t mlp_input_stats(const float *X, int64_t n, int d, float *mean, float *scale, void *ws,
+                           hipStream_t st)
+{
+    const int nb = (int)((n + STAT_ROWS - 1) / STAT_ROWS);
+    double *part = (double *)ws;
+    double *part2 = part + (size_t)nb * d;
+    hipLaunchKernelGGL(column_block_sums, dim3(nb), dim3(256), 0, st, X, n, d, part);
+    hipLaunchKernelGGL(column_means, dim3((d + 255) / 256), dim3(256), 0, st, part, nb, n, d, mean);
+    hipLaunchKernelGGL(block_sq_dev, dim3(nb), dim3(256), 0, st, X, n, d, mean, part2);
+    hipLaunchKernelGGL(rms_scale, dim3(1), dim3(64), 0, st, part2, nb, n, d, scale);
+    return hipGetLastError();
+}
+
+// The first layer's input: X itself, or its standardized rows in the workspace.
+static const float *first_input(const MlpShape &s, const float *X, const uint32_t *&idx, int B,
+                                const float *mean, const float *scale, float *ws, hipStream_t st)
+{
+    if (!mean) return X;
+    float *Xs = std_inputs(s, ws, B);
+    const int64_t t = (int64_t)B * s.d;
+    hipLaunchKernelGGL(standardize_rows, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, X, idx,
+                       B, s.d, mean, scale, Xs);
+    idx = nullptr;
+    return Xs;
 }
 
 size_t mlp_workspace_floats(const MlpShape &s, int B)
@@ -427,8 +550,10 @@ static GemmArgs mk(int M, int N, int K, const float *A, int64_t as0, int64_t as1
 }
 
 hipError_t mlp_forward(const MlpShape &s, const float *P, const float *X, const uint32_t *idx, int B,
-                       bool bf16, float *ws, float *Z_out, hipStream_t st)
+                       bool bf16, float *ws, float *Z_out, hipStream_t st, const float *mean,
+                       const float *scale)
 {
+    X = first_input(s, X, idx, B, mean, scale, ws, st);
     float *H1 = ws, *H2 = H1 + (size_t)B * s.H;
     float *Z = Z_out ? Z_out : H2 + (size_t)B * s.H * 3;
     hipError_t e;
@@ -441,14 +566,16 @@ hipError_t mlp_forward(const MlpShape &s, const float *P, const float *X, const 
 
 hipError_t mlp_gradients(const MlpShape &s, const float *P, const float *X, const uint32_t *lab,
                          const uint32_t *idx, int B, bool bf16, float *ws, float *G,
-                         float *loss_mean, hipStream_t st)
+                         float *loss_mean, hipStream_t st, const float *mean, const float *scale)
 {
     float *H1 = ws, *H2 = H1 + (size_t)B * s.H;
     float *dH2 = H2 + (size_t)B * s.H, *dH1 = dH2 + (size_t)B * s.H;
     float *Z = dH1 + (size_t)B * s.H, *dZ = Z + (size_t)B * s.K, *loss = dZ + (size_t)B * s.K;
-    hipError_t e = mlp_forward(s, P, X, idx, B, bf16, ws, Z, st);
+    const uint32_t *lab_idx = idx;  // labels stay indexed by the batch's rows
+    X = first_input(s, X, idx, B, mean, scale, ws, st);
+    hipError_t e = mlp_forward(s, P, X, idx, B, bf16, ws, Z, st, nullptr, nullptr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(softmax_xent, dim3((B + 3) / 4), dim3(256), 0, st, Z, lab, idx, B, s.K, dZ, loss);
+    hipLaunchKernelGGL(softmax_xent, dim3((B + 3) / 4), dim3(256), 0, st, Z, lab, lab_idx, B, s.K, dZ, loss);
     if (loss_mean) hipLaunchKernelGGL(mean_of, dim3(1), dim3(256), 0, st, loss, B, loss_mean);
     // layer 3: dW3 = H2^T dZ, db3 = colsum dZ, dH2 = (dZ W3^T) * (H2 > 0)
     e = gemm(mk(s.H, s.K, B, H2, 1, s.H, dZ, s.K, 1, G + s.oW3, nullptr, nullptr, 0), bf16, st, true);
@@ -479,11 +606,30 @@ hipError_t mlp_adam(const MlpShape &s, float *P, const float *G, float *M1, floa
     return hipGetLastError();
 }
 
-hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B, bool bf16,
-                       const uint32_t *entries, uint32_t fallback, float theta, float *ws,
-                       uint32_t *out, float *conf, hipStream_t st)
+// hidden [2 x B x H] = the activations as the next product reads them:
+// float32 values, rounded to bf16 first when `round` is set.
+__global__ void widen_hidden(const float *__restrict__ Hf, const uint16_t *__restrict__ Hb,
+                             int64_t m, int round, float *__restrict__ out)
 {
-    float *Z = ws + (size_t)B * s.H * 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    if (Hb) out[t] = __uint_as_float((uint32_t)Hb[t] << 16);
+    else out[t] = round ? __uint_as_float((uint32_t)bf16_bits(Hf[t]) << 16) : Hf[t];
+}
+
+// Scores Z [B x K] of the queries.  bf16: on packed operands (every operand
+// rounded to bf16 once, as gemm_kernel rounds it on load) when d and H are
+// multiples of 16, else through mlp_forward.  hidden (optional): the two
+// hidden layers as the next products read them.
+hipError_t mlp_scores(const MlpShape &s, const float *P, const float *X, int B, bool bf16,
+                      float *ws, float *Z, hipStream_t st, const float *mean, const float *scale,
+                      float *hidden)
+{
+    const int64_t bh = (int64_t)B * s.H;
+    auto widen = [&](const float *Hf, const uint16_t *Hb, float *out) {
+        hipLaunchKernelGGL(widen_hidden, dim3((unsigned)((bh + 255) / 256)), dim3(256), 0, st, Hf, Hb,
+                           bh, bf16 ? 1 : 0, out);
+    };
     hipError_t e = hipSuccess;
     if (bf16 && s.d % 16 == 0 && s.H % 16 == 0 && B > 0) {
         // packed operands: bf16 activations in the H1 / H2 areas, weights and
@@ -502,7 +648,9 @@ hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B,
         pack(P + s.oW1, s.H, s.d, 1, s.H, W1t);  // W1 (k, j) = W1[k * H + j]
         pack(P + s.oW2, s.H, s.H, 1, s.H, W2t);
         pack(P + s.oW3, s.K, s.H, 1, s.K, W3t);  // W3 (k, j) = W3[k * K + j]
-        pack(X, B, s.d, s.d, 1, Xb);
+        const int64_t tx = (int64_t)B * s.d;
+        hipLaunchKernelGGL(pack_inputs, dim3((unsigned)((tx + 255) / 256)), dim3(256), 0, st, X,
+                           (int64_t)B, s.d, mean, scale, Xb);
         auto grid = [&](int N) {
             const int64_t tiles = (int64_t)((B + 31) / 32) * ((N + 127) / 128);
             return dim3((unsigned)((tiles + 3) / 4));
@@ -513,10 +661,29 @@ hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B,
                            P + s.ob2, nullptr, H2b);
         hipLaunchKernelGGL((gemm_packed<4, false>), grid(s.K), dim3(256), 0, st, H2b, W3t, B, s.K, s.H,
                            P + s.ob3, Z, nullptr);
+        if (hidden) {
+            widen(nullptr, H1b, hidden);
+            widen(nullptr, H2b, hidden + bh);
+        }
         e = hipGetLastError();
     } else {
-        e = mlp_forward(s, P, X, nullptr, B, bf16, ws, Z, st);
+        e = mlp_forward(s, P, X, nullptr, B, bf16, ws, Z, st, mean, scale);
+        if (e == hipSuccess && hidden) {
+            widen(ws, nullptr, hidden);
+            widen(ws + bh, nullptr, hidden + bh);
+            e = hipGetLastError();
+        }
     }
+    return e;
+}
+
+hipError_t mlp_predict(const MlpShape &s, const float *P, const float *X, int B, bool bf16,
+                       const uint32_t *entries, uint32_t fallback, float theta, float *ws,
+                       uint32_t *out, float *conf, hipStream_t st, const float *mean,
+                       const float *scale)
+{
+    float *Z = ws + (size_t)B * s.H * 2;
+    hipError_t e = mlp_scores(s, P, X, B, bf16, ws, Z, st, mean, scale, nullptr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(predict_entry, dim3((B + 3) / 4), dim3(256), 0, st, Z, B, s.K, entries,
                        fallback, theta, out, conf);

@@ -4,6 +4,9 @@
 //         one float32 scale per vector s = max|x| / 448 (1 for a zero vector),
 //         code = E4M3 rounding of x / s, ties to even, saturating at +-448;
 //         the stored element stands for decode(code) * s (one float32 product).
+//         Beside s each vector keeps n2 = fl(fl(s s) dot(c, c)), c the E4M3
+//         values, dot the fixed-order dot product: the search scores fp8
+//         vectors in the dot form fma(-2 s, dot(q, c), dot(q, q) + n2).
 // Finite inputs are assumed.
 #include <hip/hip_runtime.h>
 
@@ -20,9 +23,9 @@ __global__ void quant_bf16(const float *__restrict__ x, int64_t total, uint16_t 
     if (t < total) out[t] = bf16_bits(x[t]);
 }
 
-// One wavefront per vector.
+// One wavefront per vector; sn [n x 2] receives (s, n2).
 __global__ __launch_bounds__(256) void quant_fp8(const float *__restrict__ x, int64_t n, int d,
-                                                 uint8_t *__restrict__ out, float *__restrict__ scales)
+                                                 uint8_t *__restrict__ out, float *__restrict__ sn)
 {
     const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = lane_id();
@@ -34,7 +37,22 @@ __global__ __launch_bounds__(256) void quant_fp8(const float *__restrict__ x, in
     for (int off = 32; off >= 1; off >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, off, 64));
     const float s = m > 0.f ? m / 448.0f : 1.0f;
     for (int i = lane; i < d; i += 64) out[(size_t)p * d + i] = e4m3_encode(row[i] / s);
-    if (lane == 0) scales[p] = s;
+    // dot(c, c) in the fixed order: lane l < 32 takes elements (r*32 + l)*4 .. +3
+    // for r = 0, 1, ... in increasing order, then the 16-8-4-2-1 butterfly
+    float acc = 0.f;
+    if (lane < 32) {
+        for (int i0 = lane * 4; i0 < d; i0 += 128)
+            for (int j = 0; j < 4 && i0 + j < d; ++j) {
+                const float c = e4m3_value(e4m3_encode(row[i0 + j] / s));
+                acc = __builtin_fmaf(c, c, acc);
+            }
+    }
+    acc = group_sum<32>(acc);
+    if (lane == 0) {
+        const float ss = s * s;
+        sn[2 * p] = s;
+        sn[2 * p + 1] = ss * acc;
+    }
 }
 
 }  // namespace

@@ -1,9 +1,9 @@
 """Learned entry point: k-means entry nodes, labels from the plain search,
 MLP training and gated prediction.  This module only sequences library calls;
-every computation runs in libcng's kernels, except the input standardisation
-of training (a mean and a scale, folded into the first layer afterwards).  Random draws (initial weights,
-k-means seeds, epoch permutations) come from numpy generators on the host and
-are passed in as inputs."""
+every computation runs in libcng's kernels (the input standardisation too:
+its statistics come from cng_mlp_input_stats and every network call applies
+it).  Random draws (initial weights, k-means seeds, epoch permutations) come
+from numpy generators on the host and are passed in as inputs."""
 from __future__ import annotations
 
 from dataclasses import dataclass, field
@@ -37,12 +37,17 @@ class EntryModel:
     fallback: int                  # navigating node
     theta: float = 0.0
     precision: int = 1             # 1: bf16 products, 0: float32
+    affine: tuple | None = None    # (x_mean [d], x_scale [1]) of the input standardisation
     history: list = field(default_factory=list)
 
     def predict(self, queries: torch.Tensor, theta: float | None = None):
         th = self.theta if theta is None else theta
         return L.entry_predict(self.params, self.d, self.H, self.K, queries, self.precision,
-                               self.entries, self.fallback, th)
+                               self.entries, self.fallback, th, affine=self.affine)
+
+    def logits(self, queries: torch.Tensor):
+        return L.mlp_logits(self.params, self.d, self.H, self.K, queries, self.precision,
+                            affine=self.affine)
 
 
 def kmeans_entries(points: torch.Tensor, K: int, iters: int = 20, seed: int = 1):
@@ -56,17 +61,13 @@ def train(model: EntryModel, X: torch.Tensor, labels: torch.Tensor, epochs: int 
           standardize: bool = True):
     """Adam on mini-batches drawn by a seeded permutation per epoch.
 
-    With ``standardize`` the network is trained on (X - mu) / s (mu the mean
-    query, s the root-mean-square deviation), and the affine map is then folded
-    into the first layer (W1 / s, b1 - mu W1 / s), so that prediction takes raw
-    queries.  Data of large magnitude (e.g. integers in [0, 255]) does not train
-    otherwise."""
+    With ``standardize`` the network sees (x - mean) / scale, the statistics
+    of the training queries (cng_mlp_input_stats); the model keeps them and
+    prediction applies the same map.  Data of large magnitude (e.g. integers
+    in [0, 255]) does not train otherwise."""
     n = X.shape[0]
     dev = X.device
-    if standardize:
-        mu = X.mean(0)
-        sc = float((X - mu).pow(2).mean().sqrt().clamp_min(1e-12))
-        X = ((X - mu) / sc).contiguous()
+    model.affine = L.mlp_input_stats(X) if standardize else None
     P = model.params
     G = torch.empty_like(P)
     m1 = torch.zeros_like(P)
@@ -80,16 +81,10 @@ def train(model: EntryModel, X: torch.Tensor, labels: torch.Tensor, epochs: int 
         for b0 in range(0, n - batch + 1, batch):
             idx = perm[b0:b0 + batch]
             ws = L.mlp_gradients(P, model.d, model.H, model.K, X, labels, idx, batch,
-                                 model.precision, G, loss, ws)
+                                 model.precision, G, loss, ws, affine=model.affine)
             step += 1
             L.mlp_adam(P, G, m1, m2, model.d, model.H, model.K, step, lr)
             if log_every and step % log_every == 0:
                 model.history.append((step, float(loss.item())))
         model.history.append((step, float(loss.item())))
-    if standardize:
-        d, H = model.d, model.H
-        W1 = P[: d * H].view(d, H)
-        b1 = P[d * H: d * H + H]
-        b1 -= (mu / sc) @ W1
-        W1 /= sc
     return model

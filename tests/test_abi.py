@@ -19,7 +19,7 @@ def test_exports_every_declared_symbol():
 
 def _params(**kw):
     p = dict(R=32, extra=1, C=128, alpha=1.2, tau=0.0, flags=1, Lc=0, band=0, visited_log2=0,
-             alpha_max=1.2, alpha_step=0.0)
+             alpha_max=1.2, alpha_step=0.0, pass_rows=0)
     p.update(kw)
     return _lib.BuildParams(*[p[f] for f, _ in _lib.BuildParams._fields_])
 
@@ -28,7 +28,7 @@ def _params(**kw):
                                  dict(alpha=float("nan")), dict(tau=-1.0), dict(Lc=-1),
                                  dict(visited_log2=3), dict(visited_log2=20),
                                  dict(alpha_step=-0.05), dict(alpha_step=0.05, alpha_max=1.0),
-                                 dict(alpha_step=0.05, alpha_max=float("inf"))])
+                                 dict(alpha_step=0.05, alpha_max=float("inf")), dict(pass_rows=-1)])
 def test_build_params_rejected(bad):
     nb = C.c_size_t(0)
     st = cng.lib().cng_build_workspace_size(1000, 32, C.byref(_params(**bad)), C.byref(nb))
@@ -83,11 +83,17 @@ def test_other_stages_reject():
     L = cng.lib()
     fake = C.c_void_p(0x1000)
     nb = C.c_size_t(0)
-    assert L.cng_knn_workspace_size(10, 10, 8, 0, 0, C.byref(nb)) == -1
-    assert L.cng_knn_workspace_size(10, 10, 8, 300, 0, C.byref(nb)) == -4
+    assert L.cng_knn_workspace_size(10, 10, 8, 0, 0, 0, C.byref(nb)) == -1
+    assert L.cng_knn_workspace_size(10, 10, 8, 300, 0, 0, C.byref(nb)) == -4
+    assert L.cng_knn_workspace_size(10, 10, 8, 4, 0, -1, C.byref(nb)) == -1
+    # smaller passes need less band memory
+    big, small = C.c_size_t(0), C.c_size_t(0)
+    assert L.cng_knn_workspace_size(100000, 100000, 32, 64, 0, 0, C.byref(big)) == 0
+    assert L.cng_knn_workspace_size(100000, 100000, 32, 64, 0, 1000, C.byref(small)) == 0
+    assert small.value < big.value
     # exclude_self with different row and column arrays
-    assert L.cng_knn(fake, 10, C.c_void_p(0x2000), 10, 8, 4, 1, 0, fake, fake, fake, 1 << 30, None,
-                     None) == -1
+    assert L.cng_knn(fake, 10, C.c_void_p(0x2000), 10, 8, 4, 1, 0, 0, fake, fake, fake, 1 << 30,
+                     None, None) == -1
     assert L.cng_prune(fake, 10, 8, fake, fake, 4, 5, 4, 1.2, 0.0, fake, None) == -1  # W < R
     assert L.cng_prune(fake, 10, 8, fake, fake, 4, 4, 4, -1.0, 0.0, fake, None) == -1
     assert L.cng_connect(fake, 10, 8, fake, 4, 10, 8, 0, fake, 1 << 30, None, None, None) == -1
@@ -103,7 +109,7 @@ def test_serve_config_rejected_before_any_device_call():
 
     def start(**kw):
         f = dict(points=fake, vecs=fake, dtype=0, scales=None, n=100, d=8, adj=fake, W=4, entry=0,
-                 waves=0, capacity=0, max_k=10, visited_log2=0)
+                 waves=0, capacity=0, max_k=10, visited_log2=0, arena_bytes=0, idle_checks=0)
         f.update(kw)
         cfg = ServeConfig(*[f[k] for k, _ in ServeConfig._fields_])
         return L.cng_serve_start(C.byref(cfg), C.c_void_p(fake), 1 << 20, C.byref(out))
@@ -114,3 +120,7 @@ def test_serve_config_rejected_before_any_device_call():
     assert start(max_k=300) == -4
     assert start(entry=100) == -1
     assert start(dtype=2) == -1           # fp8 without scales
+    assert start(arena_bytes=-1) == -1
+    assert start(idle_checks=-1) == -1
+    assert start(arena_bytes=16) == -1    # smaller than one query
+    assert start(arena_bytes=1 << 40) == -4

@@ -29,10 +29,10 @@ def test_entry_point_tie_and_tiny():
 
 
 # ---------------------------------------------------------------- candidates
-def gpu_knn(rows, cols, C, exclude_self, band=0):
+def gpu_knn(rows, cols, C, exclude_self, band=0, pass_rows=0):
     r = dev(rows)
     c = r if exclude_self else dev(cols)
-    ids, D, ovf = cng.knn(r, c, C, exclude_self=exclude_self, band=band)
+    ids, D, ovf = cng.knn(r, c, C, exclude_self=exclude_self, band=band, pass_rows=pass_rows)
     torch.cuda.synchronize()
     return host_ids(ids), D.cpu().numpy(), ovf
 
@@ -47,6 +47,55 @@ def test_knn_points(case):
     oids, oD = oracle.knn(x, x, C, exclude_self=True)
     assert (ids == oids).all(), np.argwhere(ids != oids)[:5]
     assert same_f32(D, f32_of(oD))
+
+
+def _multi_pass_data(form, wide, n, m, seed):
+    """Inputs that select each filter form: small integers (exact bf16), real
+    values (bf16 hi/lo split) and integers above 256 (float32 filter)."""
+    g = np.random.default_rng(seed)
+    if form == "bf16":
+        d = 200 if wide else 128
+        return (g.integers(0, 100 if wide else 256, size=(n, d)).astype(np.float32),
+                g.integers(0, 100 if wide else 256, size=(m, d)).astype(np.float32))
+    if form == "split":
+        d = 200 if wide else 32
+        return (g.standard_normal((n, d)).astype(np.float32),
+                g.standard_normal((m, d)).astype(np.float32))
+    return (g.integers(0, 600, size=(n, 16)).astype(np.float32),
+            g.integers(0, 600, size=(m, 16)).astype(np.float32))
+
+
+@pytest.mark.parametrize("form,wide", [("bf16", False), ("split", False), ("f32", False),
+                                       ("bf16", True), ("split", True)])
+@pytest.mark.parametrize("self_join", [True, False])
+def test_knn_multi_pass(form, wide, self_join):
+    """Candidate filter forced into passes of 512 rows: four to six passes,
+    the last one ragged (rows not a multiple of the 256-row workgroup).  Self
+    joins of 2600 points (d <= 128: with the locality order) and 2300 query
+    rows against 1900 columns, against the oracle bit for bit, and equal to
+    the single-pass result."""
+    n, m = (2600, 0) if self_join else (1900, 2300)
+    x, q = _multi_pass_data(form, wide, n, m, seed=len(form) * 7 + wide)
+    rows = x if self_join else q
+    C = 48
+    print(f"knn multi-pass form={form} wide={wide} self={self_join} d={x.shape[1]}", flush=True)
+    ids, D, _ = gpu_knn(rows, x, C, self_join, pass_rows=512)
+    ids1, D1, _ = gpu_knn(rows, x, C, self_join)
+    oids, oD = oracle.knn(rows, x, C, exclude_self=self_join)
+    assert (ids == oids).all(), np.argwhere(ids != oids)[:5]
+    assert same_f32(D, f32_of(oD))
+    assert (ids1 == ids).all() and same_f32(D1, D)
+
+
+def test_build_multi_pass_equals_single_pass():
+    x, _ = workloads.generate(2, n=3000, nq=1)
+    xd = dev(x)
+    a = cng.build(xd, 16, 48, 1.2, pass_rows=256)
+    b = cng.build(xd, 16, 48, 1.2)
+    torch.cuda.synchronize()
+    oadj, oe, _ = oracle.build(x, 16, 48, 1.2)
+    assert (host_ids(a.adj) == oadj).all() and (host_ids(b.adj) == oadj).all()
+    assert a.entry == b.entry == oe
 
 
 def test_knn_queries_vs_points_ragged():

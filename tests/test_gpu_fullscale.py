@@ -12,7 +12,7 @@ import torch
 import oracle
 import paper_2510_05975_amd as cng
 import workloads
-from gpu_util import dev, f32_of, host_ids, same_f32
+from gpu_util import dev, f32_of, host_ids, oracle_qsearch, same_f32
 
 pytestmark = pytest.mark.gpu
 
@@ -102,9 +102,8 @@ def test_search_quantized_sampled_full(full, dtype):
     torch.cuda.synchronize()
     ids, dists = host_ids(ids_t), d_t.cpu().numpy()
     qs = full["qs"]
-    deq, _ = oracle.dequantized(full["x"], dtype)
-    oids, od, _, _ = oracle.search_rerank(deq, full["x"], full["adj"], full["q"][qs], K, 96,
-                                          full["g"].entry)
+    oids, od, _, _ = oracle_qsearch(dtype, full["x"], full["adj"], full["q"][qs], K, 96,
+                                    full["g"].entry)
     assert (ids[qs] == oids).all()
     assert same_f32(dists[qs], f32_of(od))
 

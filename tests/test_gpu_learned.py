@@ -11,6 +11,8 @@ import workloads
 from oracle import mlp as omlp
 from paper_2510_05975_amd import _lib as L, learned
 from gpu_util import dev, dev_ids, host_ids
+import mlp_bounds
+from mlp_bounds import U
 
 pytestmark = pytest.mark.gpu
 
@@ -36,27 +38,81 @@ def net():
     return p, X, y
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-1)])
-def test_gradients_vs_oracle(net, precision, tol):
-    """float32 products: every gradient tensor within 1e-5 (relative 2-norm) of
-    float64.  bf16 products round every input to 8 significant bits (2^-8);
-    through three backward layers and batch sums with heavy cancellation the
-    stated bound is 10% relative 2-norm, with the direction kept (cosine >= 0.99)."""
+def test_gradients_fp32_vs_oracle(net):
+    """float32 products: every gradient tensor within 1e-5 (relative 2-norm)
+    of the float64 network, the loss within 1e-5 relative."""
     p, X, y = net
     P = dev(p[None])[0]
     G = torch.empty_like(P)
     loss = torch.zeros(1, device="cuda:0")
-    L.mlp_gradients(P, D, H, K, dev(X), dev_ids(y), None, 64, precision, G, loss)
+    L.mlp_gradients(P, D, H, K, dev(X), dev_ids(y), None, 64, 0, G, loss)
     torch.cuda.synchronize()
     l64, g64 = omlp.loss_and_grads(p, D, H, K, X, y)
-    assert abs(loss.item() - l64) <= min(tol, 1e-2) * abs(l64)
-    errs = []
+    assert abs(loss.item() - l64) <= 1e-5 * abs(l64)
     for a, b in zip(split(G.cpu().numpy().astype(np.float64), D, H, K), split(g64, D, H, K)):
-        cos = float(np.dot(a, b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
-        errs.append((rel(a, b), cos))
-    print(f"precision {precision}: (rel error, cosine) per tensor W1 b1 W2 b2 W3 b3: {errs}")
-    for r, c in errs:
-        assert r <= tol and c >= (0.99 if precision else 1 - 1e-8)
+        assert rel(a, b) <= 1e-5
+
+
+@pytest.mark.parametrize("standardize", [False, True])
+def test_gradients_bf16_layerwise_vs_oracle(net, standardize):
+    """One bf16 training step, product by product: from the library's own
+    operands (its stored intermediates H1, H2, Z, dZ, dH2, dH1, documented in
+    cng_mlp_gradients), every product, ReLU mask, softmax and bias sum against
+    the oracle's exact product of the same bf16 operands, within the float32
+    accumulation bound (tests/mlp_bounds.py).  With standardize the input
+    affine of cng_mlp_input_stats is applied on the device."""
+    p, X, y = net
+    B = len(X)
+    Xin = X * 40.0 + 100.0 if standardize else X
+    xd = dev(Xin)
+    aff = L.mlp_input_stats(xd) if standardize else None
+    P = dev(p[None])[0]
+    G = torch.empty_like(P)
+    loss = torch.zeros(1, device="cuda:0")
+    ws = L.mlp_gradients(P, D, H, K, xd, dev_ids(y), None, B, 1, G, loss, affine=aff)
+    torch.cuda.synchronize()
+    w = ws[: (4 * B * H + 2 * B * K + B) * 4].view(torch.float32).cpu().numpy().astype(np.float64)
+    H1, H2, dH2, dH1 = (w[i * B * H:(i + 1) * B * H].reshape(B, H) for i in range(4))
+    Z = w[4 * B * H: 4 * B * H + B * K].reshape(B, K)
+    dZ = w[4 * B * H + B * K: 4 * B * H + 2 * B * K].reshape(B, K)
+    lrow = w[4 * B * H + 2 * B * K:]
+    Xs = omlp.standardized(Xin, aff[0].cpu().numpy(), aff[1].item()) if standardize else Xin
+    Xs = Xs.astype(np.float64)
+    W1, b1, W2, b2, W3, b3 = omlp.unpack(p, D, H, K)
+    g = split(G.cpu().numpy().astype(np.float64), D, H, K)
+    checks = {}
+    v, e = mlp_bounds.relu_layer(Xs, W1, b1, False)
+    checks["H1"] = mlp_bounds.within(H1, v, e)
+    v, e = mlp_bounds.relu_layer(H1, W2, b2, False)
+    checks["H2"] = mlp_bounds.within(H2, v, e)
+    v, e = mlp_bounds.product(H2, W3, b3)
+    checks["Z"] = mlp_bounds.within(Z, v, e)
+    Pr, eP = mlp_bounds.softmax(Z)
+    t = Pr.copy()
+    t[np.arange(B), y] -= 1.0
+    checks["dZ"] = mlp_bounds.within(dZ, t / B, (eP + U * np.abs(t)) / B)
+    m = Z.max(1)
+    lo = m + np.log(np.exp(Z - m[:, None]).sum(1)) - Z[np.arange(B), y]
+    checks["loss"] = mlp_bounds.within(lrow, lo, mlp_bounds.gamma(K + 16) * (np.abs(m) + np.abs(lo) + np.abs(Z[np.arange(B), y])))
+    for name, (A, Bm, gi) in {"W3": (H2.T, dZ, 4), "W2": (H1.T, dH2, 2), "W1": (Xs.T, dH1, 0)}.items():
+        v, e = mlp_bounds.product(A, Bm)
+        checks["g" + name] = mlp_bounds.within(g[gi].reshape(v.shape), v, e)
+    for name, (Dm, gi) in {"b3": (dZ, 5), "b2": (dH2, 3), "b1": (dH1, 1)}.items():
+        v, e = mlp_bounds.colsum(Dm)
+        checks["g" + name] = mlp_bounds.within(g[gi], v, e)
+    v, e = mlp_bounds.product(dZ, W3.T)
+    checks["dH2"] = mlp_bounds.within(dH2, v * (H2 > 0), e * (H2 > 0))
+    v, e = mlp_bounds.product(dH2, W2.T)
+    checks["dH1"] = mlp_bounds.within(dH1, v * (H1 > 0), e * (H1 > 0))
+    print("bf16 step, max |lib - oracle| / bound per product:",
+          {k: round(r, 4) for k, (_, r) in checks.items()})
+    assert all(ok for ok, _ in checks.values()), checks
+    assert abs(loss.item() - lrow.mean()) <= 1e-6 * abs(lrow.mean())
+    # the whole step against the oracle's own bf16 form (not from the library's
+    # intermediates): close, not bit-identical -- reported, not a parity claim
+    _, g_o = omlp.loss_and_grads(p, D, H, K, Xs, y, rnd=omlp.round_bf16)
+    print("end to end vs the oracle's bf16 form, relative 2-norm per tensor:",
+          [round(rel(a, b), 5) for a, b in zip(g, split(g_o, D, H, K))])
 
 
 def test_logits_fp32_vs_oracle(net):
@@ -64,6 +120,69 @@ def test_logits_fp32_vs_oracle(net):
     Z = L.mlp_logits(dev(p[None])[0], D, H, K, dev(X), 0)
     _, _, Z64 = omlp.forward(p, D, H, K, X)
     assert rel(Z.cpu().numpy(), Z64) <= 1e-5
+
+
+def test_input_stats_and_affine():
+    """cng_mlp_input_stats against float64 numpy; the network with the input
+    affine equals the network on inputs standardized beforehand (float32,
+    elementwise), bit for bit, in both precisions."""
+    x, _ = workloads.generate(2, n=10000, nq=1)
+    xd = dev(x)
+    mean, scale = L.mlp_input_stats(xd)
+    m64 = x.astype(np.float64).mean(0)
+    s64 = np.sqrt(((x.astype(np.float64) - m64.astype(np.float32)) ** 2).mean())
+    np.testing.assert_allclose(mean.cpu().numpy(), m64, rtol=1e-6, atol=1e-6)
+    assert abs(scale.item() - s64) <= 1e-6 * s64
+    d, Hs, Ks = 128, 64, 48
+    p = learned.init_params(d, Hs, Ks, seed=5)
+    P = dev(p[None])[0]
+    q = x[:96]
+    xs = omlp.standardized(q, mean.cpu().numpy(), scale.item())
+    for prec in (0, 1):
+        Za = L.mlp_logits(P, d, Hs, Ks, dev(q), prec, affine=(mean, scale))
+        Zb = L.mlp_logits(P, d, Hs, Ks, dev(xs), prec)
+        assert torch.equal(Za, Zb)
+    y = np.arange(96, dtype=np.uint32) % Ks
+    Ga, Gb = torch.empty_like(P), torch.empty_like(P)
+    L.mlp_gradients(P, d, Hs, Ks, dev(q), dev_ids(y), None, 96, 1, Ga, affine=(mean, scale))
+    L.mlp_gradients(P, d, Hs, Ks, dev(xs), dev_ids(y), None, 96, 1, Gb)
+    assert torch.equal(Ga, Gb)
+
+
+def test_logits_bf16_layerwise_vs_oracle(net):
+    """The prediction path (packed bf16 operands, cng_mlp_logits with its
+    hidden activations) layer by layer against the oracle's exact products of
+    the same bf16 operands: each hidden layer within the float32 accumulation
+    bound plus its own bf16 rounding, the logits within the accumulation bound,
+    and the argmax equal wherever the top-2 gap exceeds twice the bound."""
+    p, X, _ = net
+    g = np.random.default_rng(11)
+    Xb = np.concatenate([X, g.standard_normal((448, D)).astype(np.float32)]).astype(np.float64)
+    Zt, Ht = L.mlp_logits(dev(p[None])[0], D, H, K, dev(Xb), 1, hidden=True)
+    Z = Zt.cpu().numpy().astype(np.float64)
+    H1, H2 = (h.astype(np.float64) for h in Ht.cpu().numpy())
+    W1, b1, W2, b2, W3, b3 = omlp.unpack(p, D, H, K)
+    assert (omlp.round_bf16(H1) == H1).all() and (omlp.round_bf16(H2) == H2).all()
+    v, e = mlp_bounds.relu_layer(Xb, W1, b1, True)
+    ok1, r1 = mlp_bounds.within(H1, v, e)
+    v, e = mlp_bounds.relu_layer(H1, W2, b2, True)
+    ok2, r2 = mlp_bounds.within(H2, v, e)
+    Zo, eZ = mlp_bounds.product(H2, W3, b3)
+    ok3, r3 = mlp_bounds.within(Z, Zo, eZ)
+    print(f"bf16 prediction path, max |lib - oracle| / bound: H1 {r1:.3g} H2 {r2:.3g} Z {r3:.3g}; "
+          f"median logit bound {np.median(eZ):.3g} of median |z| {np.median(np.abs(Zo)):.3g}")
+    assert ok1 and ok2 and ok3
+    rows = np.arange(len(Zo))
+    top2 = np.argsort(-Zo, axis=1)[:, :2]
+    gap = Zo[rows, top2[:, 0]] - Zo[rows, top2[:, 1]]
+    decided = gap > 2 * (eZ[rows, top2[:, 0]] + eZ[rows, top2[:, 1]])
+    assert decided.mean() > 0.9
+    assert (Z.argmax(1)[decided] == top2[decided, 0]).all()
+    # end to end against the oracle's own bf16 form: report how often the
+    # argmax agrees (bf16 rounding of the hidden layers can flip either way)
+    _, _, Ze = omlp.forward(p, D, H, K, Xb, rnd=omlp.round_bf16)
+    print(f"argmax agreement with the oracle's bf16 form: {(Ze.argmax(1) == Z.argmax(1)).mean():.4f}, "
+          f"with float64: {(omlp.forward(p, D, H, K, Xb)[2].argmax(1) == Z.argmax(1)).mean():.4f}")
 
 
 def test_batch_ids_gather_rows(net):
@@ -96,21 +215,28 @@ def test_adam_vs_oracle():
 
 
 def test_predict_and_gate(net):
+    """cng_entry_predict uses the logits of cng_mlp_logits (the same packed
+    kernels): the entry of their argmax (ties to the lower index), and the
+    softmax probability within its float32 bound; with a threshold the gate
+    falls back to the navigating node exactly where that probability is below
+    it (rows within the bound of the threshold are skipped)."""
     p, X, _ = net
     P = dev(p[None])[0]
     ents = (np.arange(K, dtype=np.uint32) * 7 + 1)
     Z = L.mlp_logits(P, D, H, K, dev(X), 1).cpu().numpy().astype(np.float64)
+    Pr, eP = mlp_bounds.softmax(Z)
+    top = Z.argmax(1)
+    rows = np.arange(len(X))
+    conf_o, econf = Pr[rows, top], eP[rows, top]
     out, conf = L.entry_predict(P, D, H, K, dev(X), 1, dev_ids(ents), 999999, 0.0)
-    am = Z.argmax(1)
-    pr = np.exp(Z - Z.max(1, keepdims=True))
-    pr = pr.max(1) / pr.sum(1)
-    assert (host_ids(out) == ents[am]).all()
-    np.testing.assert_allclose(conf.cpu().numpy(), pr, rtol=1e-4)
-    th = float(np.median(pr))
+    assert (host_ids(out) == ents[top]).all()
+    assert (np.abs(conf.cpu().numpy() - conf_o) <= econf).all()
+    th = float(np.median(conf_o))
     out2, _ = L.entry_predict(P, D, H, K, dev(X), 1, dev_ids(ents), 999999, th)
-    want = np.where(pr >= th, ents[am], 999999)
-    agree = host_ids(out2) == want
-    assert agree.mean() >= 0.95   # only probabilities within rounding of theta may differ
+    want = np.where(conf_o >= th, ents[top], 999999)
+    sure = np.abs(conf_o - th) > econf
+    assert sure.sum() >= len(X) - 2
+    assert (host_ids(out2)[sure] == want[sure]).all()
 
 
 def test_kmeans_entries_and_init():

@@ -8,9 +8,17 @@ import torch
 import oracle
 import paper_2510_05975_amd as cng
 import workloads
-from gpu_util import dev, dev_ids, f32_of, host_ids, same_f32
+from gpu_util import dev, dev_ids, f32_of, host_ids, oracle_qsearch, same_f32
 
 pytestmark = pytest.mark.gpu
+
+
+def e4m3_values(codes) -> np.ndarray:
+    """E4M3 values of uint8 codes (decoded on the host)."""
+    codes = np.asarray(codes).astype(np.uint32)
+    e, m, sgn = (codes >> 3) & 0xF, codes & 7, np.where(codes & 0x80, -1.0, 1.0)
+    val = np.where(e == 0, m * 2.0 ** -9, (8 + m) * 2.0 ** (e.astype(np.int64) - 10)) * sgn
+    return val.astype(np.float32)
 
 
 def stored_values(st: cng.Store) -> np.ndarray:
@@ -18,14 +26,12 @@ def stored_values(st: cng.Store) -> np.ndarray:
     if st.dtype == cng.BF16:
         b = st.vecs.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
         return b.view(np.float32)
-    codes = st.vecs.cpu().numpy().astype(np.uint32)
-    e, m, sgn = (codes >> 3) & 0xF, codes & 7, np.where(codes & 0x80, -1.0, 1.0)
-    val = np.where(e == 0, m * 2.0 ** -9, (8 + m) * 2.0 ** (e.astype(np.int64) - 10)) * sgn
-    return (val.astype(np.float32) * st.scales.cpu().numpy()[:, None]).astype(np.float32)
+    val = e4m3_values(st.vecs.cpu().numpy())
+    return (val * st.scales.cpu().numpy()[:, 0:1]).astype(np.float32)
 
 
 @pytest.mark.parametrize("dtype", [cng.BF16, cng.FP8])
-@pytest.mark.parametrize("cfg,n", [(1, 3000), (3, 500), (4, 2000)])
+@pytest.mark.parametrize("cfg,n", [(1, 3000), (3, 500), (4, 2000), (2, 1000)])
 def test_quantize_matches_oracle(dtype, cfg, n):
     x, _ = workloads.generate(cfg, n=n, nq=1)
     x[3] = 0.0
@@ -34,7 +40,10 @@ def test_quantize_matches_oracle(dtype, cfg, n):
     want, sc = oracle.dequantized(x, dtype)
     assert same_f32(stored_values(st), want)
     if dtype == cng.FP8:
-        assert same_f32(st.scales.cpu().numpy(), sc)
+        c, s, n2 = oracle.fp8_encode(x)
+        sn = st.scales.cpu().numpy()
+        assert same_f32(e4m3_values(st.vecs.cpu().numpy()), c)
+        assert same_f32(sn[:, 0], s) and same_f32(sn[:, 1], n2)
 
 
 def test_fp8_codes_saturate_and_keep_sign():
@@ -42,6 +51,7 @@ def test_fp8_codes_saturate_and_keep_sign():
     st = cng.quantize(dev(x), cng.FP8)
     want, _ = oracle.dequantized(x, cng.FP8)
     assert same_f32(stored_values(st), want)
+    assert same_f32(st.scales.cpu().numpy()[:, 1], oracle.fp8_encode(x)[2])
 
 
 def gpu_qsearch(x, st, adj, q, k, L, e, vlog2=14):
@@ -58,10 +68,9 @@ def test_quantized_search_bit_exact(dtype, cfg, n, R, C):
     x, q = workloads.generate(cfg, n=n, nq=120)
     adj, e, _ = oracle.build(x, R, C, 1.2)
     st = cng.quantize(dev(x), dtype)
-    deq, _ = oracle.dequantized(x, dtype)
     for L, k in [(32, 10), (64, 10), (8, 20)]:
         g = gpu_qsearch(x, st, adj, q, k, L, e)
-        o = oracle.search_rerank(deq, x, adj, q, k, L, e)
+        o = oracle_qsearch(dtype, x, adj, q, k, L, e)
         assert (g[0] == o[0]).all(), np.argwhere(g[0] != o[0])[:5]
         assert same_f32(g[1], f32_of(o[1]))
         assert (g[2] == o[2]).all() and (g[3] == o[3]).all()
@@ -73,9 +82,8 @@ def test_quantized_search_odd_dims(d):
     adj, e, _ = oracle.build(x, 10, 20, 1.2)
     for dtype in (cng.BF16, cng.FP8):
         st = cng.quantize(dev(x), dtype)
-        deq, _ = oracle.dequantized(x, dtype)
         g = gpu_qsearch(x, st, adj, q, 10, 24, e)
-        o = oracle.search_rerank(deq, x, adj, q, 10, 24, e)
+        o = oracle_qsearch(dtype, x, adj, q, 10, 24, e)
         assert (g[0] == o[0]).all() and same_f32(g[1], f32_of(o[1]))
 
 

@@ -86,3 +86,49 @@ def test_adam_second_step_closed_forms():
     np.testing.assert_allclose(m, [-(0.1 ** 2)], rtol=1e-12)
     np.testing.assert_allclose(v, [1 - 0.999 ** 2], rtol=1e-12)
     np.testing.assert_allclose(p2, p1 + lr / 19, rtol=1e-7)
+
+
+def test_round_bf16_matches_c_oracle_and_is_identity_on_bf16_values():
+    import oracle
+    g = np.random.default_rng(9)
+    v = np.concatenate([g.standard_normal(300) * 10.0 ** g.integers(-6, 6, 300),
+                        [0.0, -0.0, 1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 255.0, 257.0]])
+    r = mlp.round_bf16(v)
+    assert all(r[i] == oracle.round_bf16(float(np.float32(v[i]))) for i in range(len(v)))
+    assert (mlp.round_bf16(r) == r).all()
+    assert mlp.round_bf16([1.0 + 2 ** -8])[0] == 1.0           # tie to even
+    assert mlp.round_bf16([1.0 + 3 * 2 ** -8])[0] == 1.0 + 2 ** -6
+
+
+def test_bf16_form_equals_float64_on_bf16_representable_operands():
+    """With operands that bf16 holds exactly (small dyadic values) and
+    activations that stay so, the bf16 form is the float64 network."""
+    g = np.random.default_rng(4)
+    d, H, K, B = 4, 6, 5, 7
+    n = d * H + H + H * H + H + H * K + K
+    p = g.integers(-3, 4, n) / 4.0
+    X = g.integers(-2, 3, (B, d)).astype(np.float64)
+    y = g.integers(0, K, B)
+    _, _, Z = mlp.forward(p, d, H, K, X)
+    _, _, Zb = mlp.forward(p, d, H, K, X, rnd=mlp.round_bf16)
+    H1, H2, _ = mlp.forward(p, d, H, K, X)
+    assert (mlp.round_bf16(H1) == H1).all() and (mlp.round_bf16(H2) == H2).all()
+    assert (Z == Zb).all()
+    # and rounding changes the result where the operands are not bf16 values
+    p2 = p + 1e-3
+    _, _, Z2 = mlp.forward(p2, d, H, K, X)
+    _, _, Z2b = mlp.forward(p2, d, H, K, X, rnd=mlp.round_bf16)
+    assert not (Z2 == Z2b).all()
+    l1, g1 = mlp.loss_and_grads(p, d, H, K, X, y)
+    l2, g2 = mlp.loss_and_grads(p, d, H, K, X, y, rnd=lambda a: np.asarray(a, np.float64))
+    assert l1 == l2 and (g1 == g2).all()
+
+
+def test_standardized_is_float32_elementwise():
+    X = np.array([[1.0, 2.0], [3.0, 7.0]], np.float32)
+    m = np.array([2.0, 4.5], np.float32)
+    s = np.float32(3.0)
+    out = mlp.standardized(X, m, s)
+    assert out.dtype == np.float32
+    assert out[0, 0] == np.float32(-1.0) / np.float32(3.0)
+    assert out[1, 1] == np.float32(2.5) / np.float32(3.0)
