@@ -89,6 +89,16 @@ def lib():
         L.orc_search_fp8.argtypes = [f32p, f32p, f32p, C.c_void_p, i64, C.c_int, u32p, C.c_int, f32p,
                                      i64, C.c_int, C.c_int, u32p, i64, u32p, f64p, C.c_void_p,
                                      C.c_void_p]
+        L.orc_splitmix.restype = C.c_uint64
+        L.orc_splitmix.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_nndescent.argtypes = [f32p, i64, C.c_int, C.c_int, C.c_uint64, C.c_int, C.c_int, u32p,
+                                    f64p, C.POINTER(C.c_int)]
+        L.orc_graph_candidates.argtypes = [f32p, i64, C.c_int, u32p, C.c_int, C.c_uint32, C.c_int,
+                                           C.c_int, C.c_int, u32p, f64p]
+        L.orc_build_ex.argtypes = [f32p, i64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                   C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_int, C.c_uint64, C.c_int, C.c_int, u32p,
+                                   C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -219,19 +229,52 @@ def backward(points, adj, R: int, Cb: int, alpha: float, tau: float = 0.0, mode:
 
 def build(points, R: int, C_: int, alpha: float, tau: float = 0.0, mode: int = FP32,
           connect: bool = True, Lc: int = 0, extra: int = 1, backward: bool = False,
-          alpha_max: float | None = None, alpha_step: float = 0.0):
+          alpha_max: float | None = None, alpha_step: float = 0.0, knn_K: int = 0,
+          knn_seed: int = 0, knn_rounds: int = 0, cand_L: int = 0):
     """Whole build -> (adj (n x (R + extra)), entry, n_added).  alpha_step > 0:
-    adaptive alpha (Alg. 4) from ``alpha`` to ``alpha_max``."""
+    adaptive alpha (Alg. 4) from ``alpha`` to ``alpha_max``.  knn_K > 0:
+    candidates from an NN-descent graph (K, seed, rounds) searched with beam
+    cand_L (Alg. 3 phases 1-2) instead of the exact C nearest."""
     points = _f32(points)
     n, d = points.shape
     adj = np.empty((n, R + extra), np.uint32)
     entry = C.c_uint32(0)
     added = C.c_int64(0)
     amax = alpha if alpha_max is None else alpha_max
-    _check(lib().orc_build(points, n, d, R, extra, C_, alpha, amax, alpha_step, tau, mode,
-                           int(connect), int(backward), Lc, adj, C.byref(entry), C.byref(added)),
-           "build")
+    _check(lib().orc_build_ex(points, n, d, R, extra, C_, alpha, amax, alpha_step, tau, mode,
+                              int(connect), int(backward), Lc, knn_K, knn_seed, knn_rounds, cand_L,
+                              adj, C.byref(entry), C.byref(added)), "build")
     return adj, int(entry.value), added.value
+
+
+def splitmix(seed: int, i: int) -> int:
+    """Output i of the counter-based SplitMix64 stream with seed ``seed``."""
+    return int(lib().orc_splitmix(seed & (2 ** 64 - 1), i))
+
+
+def nndescent(points, K: int, seed: int, rounds: int, mode: int = FP32):
+    """Alg. 3 phase 1: NN-descent K-NN graph -> (ids [n, K], D [n, K], rounds run)."""
+    points = _f32(points)
+    n, d = points.shape
+    ids = np.empty((n, K), np.uint32)
+    D = np.empty((n, K), np.float64)
+    rr = C.c_int(0)
+    _check(lib().orc_nndescent(points, n, d, K, seed & (2 ** 64 - 1), rounds, mode, ids, D,
+                               C.byref(rr)), "nndescent")
+    return ids, D, rr.value
+
+
+def graph_candidates(points, g0, entry: int, L: int, C_: int, mode: int = FP32):
+    """Alg. 3 phase 2: the C nearest of the points a beam search on g0 from
+    ``entry`` evaluates for each point (itself excluded) -> (ids, D)."""
+    points = _f32(points)
+    n, d = points.shape
+    g0 = np.ascontiguousarray(g0, np.uint32)
+    ids = np.empty((n, C_), np.uint32)
+    D = np.empty((n, C_), np.float64)
+    _check(lib().orc_graph_candidates(points, n, d, g0, g0.shape[1], entry, L, C_, mode, ids, D),
+           "graph_candidates")
+    return ids, D
 
 
 def reachable(adj, entry: int) -> np.ndarray:

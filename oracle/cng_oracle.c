@@ -948,25 +948,217 @@ done:
 }
 
 /* ------------------------------------------------------------------------- */
+/* Alg. 3 phases 1-2 with sub-quadratic candidates (Section 4.1): an           */
+/* approximate K-NN graph G0, then each point's local-neighbour set from a     */
+/* beam search on G0.                                                          */
+/* ------------------------------------------------------------------------- */
+
+/* SplitMix64 (Steele, Lea and Flood, 2014) used as a counter-based generator:
+ * output i of the stream with seed s is mix(s + (i + 1) * 0x9E3779B97F4A7C15),
+ * mix(z) = z3 ^ (z3 >> 31) with z1 = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9,
+ * z2 = z1, z3 = (z2 ^ (z2 >> 27)) * 0x94D049BB133111EB. */
+uint64_t orc_splitmix(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static int cmp_u32(const void *a, const void *b)
+{
+    const uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+/* The K nearest (D, id) of the distinct ids in ids[0..m) other than p, into
+ * out / outD (ORC_NONE / +inf padded).  ids is reordered. */
+static void top_k_of(const float *pts, int d, uint32_t p, uint32_t *ids, int64_t m, int K, int mode,
+                     orc_key *tmp, uint32_t *out, double *outD)
+{
+    qsort(ids, (size_t)m, sizeof(uint32_t), cmp_u32);
+    int64_t nt = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (ids[i] == p || ids[i] == ORC_NONE || (i > 0 && ids[i] == ids[i - 1])) continue;
+        tmp[nt].id = ids[i];
+        tmp[nt].D = dist_mode(pts + (size_t)p * d, pts + (size_t)ids[i] * d, d, mode);
+        ++nt;
+    }
+    qsort(tmp, (size_t)nt, sizeof(orc_key), cmp_key);
+    for (int j = 0; j < K; ++j) {
+        out[j] = j < nt ? tmp[j].id : ORC_NONE;
+        outD[j] = j < nt ? tmp[j].D : INFINITY;
+    }
+}
+
+/* Phase 1: approximate K-NN graph G0 by NN-descent in synchronous rounds.
+ * Start: the list of p is the K nearest by (D, id) of the distinct points
+ * orc_splitmix(seed, p K + j) mod n (j < K) other than p.  Round: every list
+ * becomes the K nearest by (D, id) of itself together with the lists of its
+ * members (neighbours of neighbours), p excluded, all read from the lists as
+ * they were when the round began.  Stops after `rounds` rounds or after a
+ * round that changed no list.  knn / knnD [n x K] (NONE / +inf padded). */
+int orc_nndescent(const float *pts, int64_t n, int d, int K, uint64_t seed, int rounds, int mode,
+                  uint32_t *knn, double *knnD, int *rounds_run)
+{
+    if (n < 1 || d < 1 || K < 1 || rounds < 0) return ORC_EINVAL;
+    const int64_t cap = (int64_t)K + (int64_t)K * K;
+    uint32_t *prev = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * K);
+    if (!prev) return ORC_ENOMEM;
+    int fail = 0;
+#pragma omp parallel
+    {
+        uint32_t *ids = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap);
+        orc_key *tmp = (orc_key *)malloc(sizeof(orc_key) * (size_t)cap);
+        if (!ids || !tmp) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < n; ++p) {
+            if (!ids || !tmp) continue;
+            for (int j = 0; j < K; ++j)
+                ids[j] = (uint32_t)(orc_splitmix(seed, (uint64_t)p * K + j) % (uint64_t)n);
+            top_k_of(pts, d, (uint32_t)p, ids, K, K, mode, tmp, knn + (size_t)p * K,
+                     knnD + (size_t)p * K);
+        }
+        free(ids);
+        free(tmp);
+    }
+    int r = 0;
+    while (!fail && r < rounds) {
+        memcpy(prev, knn, sizeof(uint32_t) * (size_t)n * K);
+        int64_t changed = 0;
+#pragma omp parallel
+        {
+            uint32_t *ids = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap);
+            orc_key *tmp = (orc_key *)malloc(sizeof(orc_key) * (size_t)cap);
+            if (!ids || !tmp) {
+#pragma omp atomic write
+                fail = 1;
+            }
+#pragma omp for schedule(dynamic, 64) reduction(+ : changed)
+            for (int64_t p = 0; p < n; ++p) {
+                if (!ids || !tmp) continue;
+                int64_t m = 0;
+                const uint32_t *own = prev + (size_t)p * K;
+                for (int j = 0; j < K; ++j) {
+                    const uint32_t u = own[j];
+                    ids[m++] = u;
+                    if (u == ORC_NONE) continue;
+                    for (int i = 0; i < K; ++i) ids[m++] = prev[(size_t)u * K + i];
+                }
+                uint32_t *out = knn + (size_t)p * K;
+                top_k_of(pts, d, (uint32_t)p, ids, m, K, mode, tmp, out, knnD + (size_t)p * K);
+                for (int j = 0; j < K; ++j)
+                    if (out[j] != own[j]) { ++changed; break; }
+            }
+            free(ids);
+            free(tmp);
+        }
+        ++r;
+        if (changed == 0) break;
+    }
+    free(prev);
+    if (rounds_run) *rounds_run = r;
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* Phase 2: the local-neighbour set of every point from G0 (rows of width Kg,
+ * NONE terminated): the C nearest (D, id), p excluded, of the points that
+ * beam-search(G0, x_p, s, L, C + 1) evaluates together with p's own G0 row
+ * (the pool of the NSG framework the paper follows; it keeps a point's K-NN
+ * neighbours when G0 does not lead from s to it, as between clusters).  With a
+ * beam of max(L, C + 1) entries the nearest evaluated points are the first of
+ * its final beam (an evaluated point leaves the beam, or never enters it,
+ * only for nearer ones).  cand / candD [n x C] (NONE / +inf padded). */
+int orc_graph_candidates(const float *pts, int64_t n, int d, const uint32_t *g0, int Kg, uint32_t s,
+                         int L, int C, int mode, uint32_t *cand, double *candD)
+{
+    if (n < 1 || d < 1 || Kg < 1 || C < 1 || L < 1 || (int64_t)s >= n) return ORC_EINVAL;
+    const int Leff = L > C + 1 ? L : C + 1;
+    int fail = 0;
+#pragma omp parallel
+    {
+        orc_beam b;
+        int ok = beam_init(&b, n, Leff + Kg + 1);
+        orc_key *pool = (orc_key *)malloc(sizeof(orc_key) * (size_t)(Leff + Kg));
+        if (!ok || !pool) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < n; ++p) {
+            if (!ok || !pool) continue;
+            const orc_scorer sc = {pts, NULL, NULL, mode};
+            const float *xp = pts + (size_t)p * d;
+            int qn = beam_one(&b, &sc, n, d, g0, Kg, xp, s, Leff, NULL, NULL, NULL, 0, NULL);
+            int m = 0;
+            for (int j = 0; j < qn; ++j) {
+                pool[m].id = b.id[j];
+                pool[m].D = b.D[j];
+                ++m;
+            }
+            for (int j = 0; j < Kg; ++j) {
+                const uint32_t v = g0[(size_t)p * Kg + j];
+                if (v == ORC_NONE || (int64_t)v >= n) break;
+                pool[m].id = v;
+                pool[m].D = dist_mode(xp, pts + (size_t)v * d, d, mode);
+                ++m;
+            }
+            qsort(pool, (size_t)m, sizeof(orc_key), cmp_key);
+            int w = 0;
+            for (int j = 0; j < m && w < C; ++j) {
+                if (pool[j].id == (uint32_t)p) continue;
+                if (j > 0 && pool[j].id == pool[j - 1].id) continue;  /* equal keys are adjacent */
+                cand[(size_t)p * C + w] = pool[j].id;
+                candD[(size_t)p * C + w] = pool[j].D;
+                ++w;
+            }
+            for (; w < C; ++w) {
+                cand[(size_t)p * C + w] = ORC_NONE;
+                candD[(size_t)p * C + w] = INFINITY;
+            }
+        }
+        beam_free(&b);
+        free(pool);
+    }
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Whole build: entry point, exact candidates, pruning of each candidate list  */
 /* (Alg. 2 with cap R and fixed alpha, or Alg. 4's adaptive alpha when         */
 /* dalpha > 0), optionally backward edges with lazy pruning (phase 3, the same */
 /* pruning), then connectivity.  Rows have width R + extra; the extra slots    */
 /* only ever hold connectivity edges.                                           */
 /* ------------------------------------------------------------------------- */
-int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, double alpha,
-              double alpha_max, double dalpha, double tau, int mode, int connect, int backward,
-              int Lc, uint32_t *adj, uint32_t *entry, int64_t *n_added)
+int orc_build_ex(const float *pts, int64_t n, int d, int R, int extra, int C, double alpha,
+                 double alpha_max, double dalpha, double tau, int mode, int connect, int backward,
+                 int Lc, int knn_K, uint64_t knn_seed, int knn_rounds, int cand_L, uint32_t *adj,
+                 uint32_t *entry, int64_t *n_added)
 {
     if (n < 2 || d < 1 || R < 1 || extra < 0 || C < 1) return ORC_EINVAL;
     int W = R + extra;
     int Ce = (int64_t)C > n - 1 ? (int)(n - 1) : C;
     uint32_t *cand = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * Ce);
     double *cD = (double *)malloc(sizeof(double) * (size_t)n * Ce);
+    uint32_t *g0 = NULL;
+    double *g0D = NULL;
     int rc = ORC_OK;
     if (!cand || !cD) { rc = ORC_ENOMEM; goto out; }
     *entry = orc_medoid(pts, n, d);
-    rc = orc_knn(pts, n, pts, n, d, Ce, 1, mode, cand, cD);
+    if (knn_K > 0) {
+        /* phases 1-2: NN-descent graph, candidates from a beam search on it */
+        g0 = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * knn_K);
+        g0D = (double *)malloc(sizeof(double) * (size_t)n * knn_K);
+        if (!g0 || !g0D) { rc = ORC_ENOMEM; goto out; }
+        rc = orc_nndescent(pts, n, d, knn_K, knn_seed, knn_rounds, mode, g0, g0D, NULL);
+        if (rc) goto out;
+        rc = orc_graph_candidates(pts, n, d, g0, knn_K, *entry, cand_L, Ce, mode, cand, cD);
+    } else {
+        rc = orc_knn(pts, n, pts, n, d, Ce, 1, mode, cand, cD);
+    }
     if (rc) goto out;
     rc = orc_prune_adaptive(pts, n, d, cand, cD, Ce, R, W, alpha, alpha_max, dalpha, tau, mode,
                             adj);
@@ -978,5 +1170,15 @@ int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, doubl
 out:
     free(cand);
     free(cD);
+    free(g0);
+    free(g0D);
     return rc;
+}
+
+int orc_build(const float *pts, int64_t n, int d, int R, int extra, int C, double alpha,
+              double alpha_max, double dalpha, double tau, int mode, int connect, int backward,
+              int Lc, uint32_t *adj, uint32_t *entry, int64_t *n_added)
+{
+    return orc_build_ex(pts, n, d, R, extra, C, alpha, alpha_max, dalpha, tau, mode, connect,
+                        backward, Lc, 0, 0, 0, 0, adj, entry, n_added);
 }
