@@ -52,6 +52,9 @@ typedef enum {
 /* Build flags */
 #define CNG_BUILD_CONNECT 1u  /* run the connectivity phase (Algorithm 3, phase 4) */
 #define CNG_BUILD_BACKWARD 2u /* backward edges with lazy pruning (Algorithm 3, phase 3) */
+#define CNG_BUILD_GRAPH_CANDIDATES 4u /* sub-quadratic candidates (Algorithm 3, phases 1-2):
+                                         an NN-descent K-NN graph and a beam search on it,
+                                         instead of the exact C nearest neighbours */
 
 typedef struct {
     int32_t R;           /* out-degree cap of pruning (Algorithm 2 keeps at most R), >= 1 */
@@ -69,6 +72,11 @@ typedef struct {
     int32_t pass_rows;   /* rows per pass of the candidate filter, >= 0 (0 = sized from a band
                             memory budget); rounded up to whole workgroups of 256 rows.  Only
                             splits the work: candidate lists do not depend on it */
+    /* CNG_BUILD_GRAPH_CANDIDATES (see cng_nndescent, cng_graph_candidates): */
+    int32_t knn_K;       /* degree of the K-NN graph, 1..64 (0 = 32); C + 1 + knn_K <= 256 */
+    int32_t knn_rounds;  /* most NN-descent rounds (0 = 12) */
+    int32_t cand_L;      /* beam width of the candidate searches (0 = C), <= 512 */
+    uint64_t knn_seed;   /* seed of the NN-descent start (SplitMix64 stream) */
 } cng_build_params;
 
 typedef struct {
@@ -79,6 +87,8 @@ typedef struct {
     int32_t exact_integer;     /* 1 if the filter ran in exact small-integer mode */
     int32_t filter_dtype;      /* 0 = fp32 MFMA filter, 1 = bf16 MFMA filter */
     double ms_backward;        /* wall time of the backward-edge phase (0 if not run) */
+    double ms_knn_graph;       /* CNG_BUILD_GRAPH_CANDIDATES: NN-descent part of ms_candidates */
+    int32_t knn_rounds_run;    /* NN-descent rounds run */
 } cng_build_stats;
 
 /* ------------------------------------------------------------------ build */
@@ -125,6 +135,34 @@ cng_status cng_knn(const float *rows, int64_t nr, const float *cols, int64_t nc,
                    int32_t C, int32_t exclude_self, int32_t band, int64_t pass_rows, uint32_t *ids,
                    float *D, void *workspace, size_t workspace_bytes, void *stream,
                    int64_t *overflow_rows_host);
+
+/* Stage: approximate K-NN graph by NN-descent (Algorithm 3, phase 1).
+ * Synchronous rounds: a point's list starts as the K nearest by (D, id) of
+ * the distinct points splitmix64(seed, p K + j) mod n, j < K, other than p
+ * (output i of the SplitMix64 stream with seed s is the SplitMix64 mix of
+ * s + (i + 1) 0x9E3779B97F4A7C15); each round replaces every list by the K
+ * nearest of itself and the lists of its members, all read from the lists as
+ * they were when the round began.  Stops after `rounds` rounds or after a
+ * round that changed no list (rounds_host: rounds run).
+ *   ids [n x K] uint32 ascending (D, id), CNG_NONE padded; D [n x K] float32.
+ *   1 <= K <= 64.  Synchronises `stream`. */
+cng_status cng_nndescent_workspace_size(int64_t n, int32_t K, size_t *bytes_host);
+cng_status cng_nndescent(const float *points, int64_t n, int32_t d, int32_t K, uint64_t seed,
+                         int32_t rounds, uint32_t *ids, float *D, void *workspace,
+                         size_t workspace_bytes, void *stream, int32_t *rounds_host);
+
+/* Stage: local-neighbour sets from a graph (Algorithm 3, phase 2).  For every
+ * point p the C nearest by (D, id), p excluded, of the points that
+ * beam-search(G0, x_p, s, L, C + 1) evaluates together with p's own row of
+ * G0 (the pool of the NSG framework: it keeps the K-NN neighbours where G0
+ * does not lead from s to p).  G0: g0 [n x K] with distances g0D (as
+ * cng_nndescent returns them).  cand [n x C], candD [n x C] as cng_knn.
+ * C + 1 + K <= 256, max(L, C + 1) <= 512.  Synchronises `stream`. */
+cng_status cng_graph_candidates_workspace_size(int64_t n, int32_t C, size_t *bytes_host);
+cng_status cng_graph_candidates(const float *points, int64_t n, int32_t d, const uint32_t *g0,
+                                const float *g0D, int32_t K, uint32_t entry, int32_t L, int32_t C,
+                                uint32_t *cand, float *candD, void *workspace,
+                                size_t workspace_bytes, void *stream);
 
 /* Stage: pruning (Algorithm 2 with Eq. (1), fixed alpha, at most R kept).
  *   cand [n x C] candidate ids of every point, ascending by (D, id), CNG_NONE

@@ -23,6 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "cng.h")
 NONE = 0xFFFFFFFF
 BUILD_CONNECT = 1
 BUILD_BACKWARD = 2
+BUILD_GRAPH_CANDIDATES = 4
 STATUS = {0: "CNG_OK", -1: "CNG_EINVAL", -2: "CNG_ENOMEM", -3: "CNG_EDEVICE",
           -4: "CNG_EUNSUPPORTED", -5: "CNG_ECAPACITY"}
 
@@ -37,7 +38,8 @@ class BuildParams(C.Structure):
     _fields_ = [("R", C.c_int32), ("extra", C.c_int32), ("C", C.c_int32), ("alpha", C.c_double),
                 ("tau", C.c_double), ("flags", C.c_uint32), ("Lc", C.c_int32), ("band", C.c_int32),
                 ("visited_log2", C.c_int32), ("alpha_max", C.c_double), ("alpha_step", C.c_double),
-                ("pass_rows", C.c_int32)]
+                ("pass_rows", C.c_int32), ("knn_K", C.c_int32), ("knn_rounds", C.c_int32),
+                ("cand_L", C.c_int32), ("knn_seed", C.c_uint64)]
 
 
 class BuildStats(C.Structure):
@@ -45,7 +47,8 @@ class BuildStats(C.Structure):
                 ("ms_connect", C.c_double), ("ms_total", C.c_double),
                 ("connect_rounds", C.c_int64), ("connect_added", C.c_int64),
                 ("overflow_rows", C.c_int64), ("exact_integer", C.c_int32),
-                ("filter_dtype", C.c_int32), ("ms_backward", C.c_double)]
+                ("filter_dtype", C.c_int32), ("ms_backward", C.c_double),
+                ("ms_knn_graph", C.c_double), ("knn_rounds_run", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -65,6 +68,12 @@ _SIGS = {
     "cng_knn_workspace_size": (C.c_int, [i64, i64, i32, i32, i32, i64, C.POINTER(sz)]),
     "cng_knn": (C.c_int, [vp, i64, vp, i64, i32, i32, i32, i32, i64, vp, vp, vp, sz, vp,
                           C.POINTER(i64)]),
+    "cng_nndescent_workspace_size": (C.c_int, [i64, i32, C.POINTER(sz)]),
+    "cng_nndescent": (C.c_int, [vp, i64, i32, i32, C.c_uint64, i32, vp, vp, vp, sz, vp,
+                                C.POINTER(i32)]),
+    "cng_graph_candidates_workspace_size": (C.c_int, [i64, i32, C.POINTER(sz)]),
+    "cng_graph_candidates": (C.c_int, [vp, i64, i32, vp, vp, i32, u32, i32, i32, vp, vp, vp, sz,
+                                       vp]),
     "cng_prune": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]),
     "cng_prune_adaptive": (C.c_int, [vp, i64, i32, vp, vp, i32, i32, i32, C.c_double, C.c_double,
                                      C.c_double, C.c_double, vp, vp]),
@@ -180,15 +189,18 @@ class Graph:
 def build(points: torch.Tensor, R: int, C_: int, alpha: float, tau: float = 0.0, extra: int = 1,
           connect: bool = True, Lc: int = 0, band: int = 0, visited_log2: int = 0,
           backward: bool = False, alpha_max: float | None = None,
-          alpha_step: float = 0.0, pass_rows: int = 0) -> Graph:
-    """cng_build: entry point, exact candidates, pruning (adaptive alpha when
+          alpha_step: float = 0.0, pass_rows: int = 0, graph_candidates: bool = False,
+          knn_K: int = 0, knn_rounds: int = 0, cand_L: int = 0, knn_seed: int = 0) -> Graph:
+    """cng_build: entry point, candidates (exact, or with graph_candidates from
+    an NN-descent graph and a beam search on it), pruning (adaptive alpha when
     alpha_step > 0), optional backward edges, connectivity."""
     x = _f32(points)
     n, d = x.shape
-    flags = (BUILD_CONNECT if connect else 0) | (BUILD_BACKWARD if backward else 0)
+    flags = ((BUILD_CONNECT if connect else 0) | (BUILD_BACKWARD if backward else 0) |
+             (BUILD_GRAPH_CANDIDATES if graph_candidates else 0))
     amax = alpha if alpha_max is None else alpha_max
     p = BuildParams(R, extra, C_, alpha, tau, flags, Lc, band, visited_log2, amax, alpha_step,
-                    pass_rows)
+                    pass_rows, knn_K, knn_rounds, cand_L, knn_seed)
     nb = sz(0)
     _check("cng_build_workspace_size", lib().cng_build_workspace_size(n, d, C.byref(p), C.byref(nb)))
     ws = _ws(nb.value, x.device)
@@ -229,6 +241,39 @@ def knn(rows: torch.Tensor, cols: torch.Tensor, C_: int, exclude_self: bool = Fa
     _check("cng_knn", lib().cng_knn(rp, nr, cp, nc, d, C_, int(exclude_self), band, pass_rows, _ptr(ids),
                                     _ptr(D), _ptr(ws), nb.value, _stream(), C.byref(ovf)))
     return ids, D, ovf.value
+
+
+def nndescent(points: torch.Tensor, K: int, seed: int, rounds: int):
+    """cng_nndescent -> (ids int32 [n, K], D float32 [n, K], rounds run)."""
+    x = _f32(points)
+    n, d = x.shape
+    nb = sz(0)
+    _check("cng_nndescent_workspace_size", lib().cng_nndescent_workspace_size(n, K, C.byref(nb)))
+    ws = _ws(nb.value, x.device)
+    ids = torch.empty((n, K), dtype=torch.int32, device=x.device)
+    D = torch.empty((n, K), dtype=torch.float32, device=x.device)
+    rr = i32(0)
+    _check("cng_nndescent", lib().cng_nndescent(_ptr(x), n, d, K, seed, rounds, _ptr(ids), _ptr(D),
+                                                _ptr(ws), nb.value, _stream(), C.byref(rr)))
+    return ids, D, rr.value
+
+
+def graph_candidates(points: torch.Tensor, g0: torch.Tensor, g0D: torch.Tensor, entry: int, L: int,
+                     C_: int):
+    """cng_graph_candidates -> (ids int32 [n, C], D float32 [n, C])."""
+    x = _f32(points)
+    n, d = x.shape
+    g0 = _ids(g0)
+    nb = sz(0)
+    _check("cng_graph_candidates_workspace_size",
+           lib().cng_graph_candidates_workspace_size(n, C_, C.byref(nb)))
+    ws = _ws(nb.value, x.device)
+    ids = torch.empty((n, C_), dtype=torch.int32, device=x.device)
+    D = torch.empty((n, C_), dtype=torch.float32, device=x.device)
+    _check("cng_graph_candidates", lib().cng_graph_candidates(
+        _ptr(x), n, d, _ptr(g0), _ptr(g0D.contiguous()), g0.shape[1], entry, L, C_, _ptr(ids),
+        _ptr(D), _ptr(ws), nb.value, _stream()))
+    return ids, D
 
 
 def prune(points: torch.Tensor, cand: torch.Tensor, candD: torch.Tensor, R: int, alpha: float,

@@ -80,8 +80,10 @@ cng_status check_adaptive(double alpha0, double alpha_max, double alpha_step)
 
 struct BuildSizes {
     int Ceff, W, Lc;
+    bool graph;             // CNG_BUILD_GRAPH_CANDIDATES
+    int gK, gRounds, gL;    // its K-NN graph degree, rounds and beam width
     cng::KnnPlan knn;
-    size_t cand_ids, cand_D, entry, connect, backward, total;
+    size_t cand_ids, cand_D, g0, entry, connect, backward, total;
 };
 
 cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSizes *z)
@@ -109,17 +111,38 @@ cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSiz
     z->Lc = p->Lc > 0 ? p->Lc : z->Ceff;
     if (z->Lc > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "Lc=%d exceeds %d", z->Lc, MAX_LEFF);
     if (p->pass_rows < 0) return fail(CNG_EINVAL, "pass_rows=%d must be >= 0", p->pass_rows);
-    z->knn = cng::knn_plan(n, n, d, z->Ceff, p->band, p->pass_rows);
+    z->graph = (p->flags & CNG_BUILD_GRAPH_CANDIDATES) != 0;
+    z->gK = p->knn_K > 0 ? p->knn_K : 32;
+    z->gRounds = p->knn_rounds > 0 ? p->knn_rounds : 12;
+    z->gL = p->cand_L > 0 ? p->cand_L : z->Ceff;
+    if (z->graph) {
+        if (p->knn_K < 0 || z->gK > 64) return fail(CNG_EUNSUPPORTED, "knn_K=%d must be in [0, 64]", p->knn_K);
+        if ((int64_t)z->gK > n - 1) z->gK = (int)(n - 1);
+        if (p->knn_rounds < 0 || p->cand_L < 0) return fail(CNG_EINVAL, "knn_rounds and cand_L must be >= 0");
+        if (z->Ceff + 1 + z->gK > 256) return fail(CNG_EUNSUPPORTED, "C + 1 + knn_K exceeds 256");
+        if ((z->gL > z->Ceff + 1 ? z->gL : z->Ceff + 1) > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "cand_L exceeds %d", MAX_LEFF);
+    }
     z->cand_ids = align256((size_t)n * z->Ceff * 4);
     z->cand_D = align256((size_t)n * z->Ceff * 4);
     z->entry = align256(cng::entry_workspace_bytes(n, d));
     z->connect = align256(cng::connect_workspace_bytes(n, z->W, z->Lc));
     z->backward = (p->flags & CNG_BUILD_BACKWARD) ? align256(cng::backward_workspace_bytes(n, z->W)) : 0;
     size_t scratch = z->entry;
-    if (z->knn.bytes > scratch) scratch = z->knn.bytes;
+    if (z->graph) {
+        z->knn = cng::KnnPlan{};
+        z->g0 = align256((size_t)n * z->gK * 4) * 2;  // the K-NN graph: ids and D
+        const size_t a = align256(cng::nndescent_workspace_bytes(n, z->gK));
+        const size_t b = align256(cng::graph_candidates_workspace_bytes(n, z->Ceff));
+        if (a > scratch) scratch = a;
+        if (b > scratch) scratch = b;
+    } else {
+        z->knn = cng::knn_plan(n, n, d, z->Ceff, p->band, p->pass_rows);
+        z->g0 = 0;
+        if (z->knn.bytes > scratch) scratch = z->knn.bytes;
+    }
     if (z->connect > scratch) scratch = z->connect;
     if (z->backward > scratch) scratch = z->backward;
-    z->total = z->cand_ids + z->cand_D + align256(scratch);
+    z->total = z->cand_ids + z->cand_D + z->g0 + align256(scratch);
     return CNG_OK;
 }
 
@@ -157,7 +180,9 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
     unsigned char *w = (unsigned char *)workspace;
     uint32_t *cand = (uint32_t *)w;
     float *candD = (float *)(w + z.cand_ids);
-    void *scratch = w + z.cand_ids + z.cand_D;
+    uint32_t *g0 = (uint32_t *)(w + z.cand_ids + z.cand_D);
+    float *g0D = (float *)(w + z.cand_ids + z.cand_D + z.g0 / 2);
+    void *scratch = w + z.cand_ids + z.cand_D + z.g0;
     cng_build_stats local{};
     cng_build_stats *S = stats ? stats : &local;
     std::memset(S, 0, sizeof *S);
@@ -175,10 +200,26 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
 
     int64_t ovf = 0;
     int exact = 0, dtype = 0;
-    e = cng::launch_knn(points, n, points, n, d, z.Ceff, 1, z.knn, cand, candD, scratch, st, &ovf,
-                        &exact, &dtype);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "candidates");
+    double tg = t1;
+    int rounds_run = 0;
+    if (z.graph) {
+        // phases 1-2: NN-descent graph, then each point's candidates from a
+        // beam search on it
+        e = cng::run_nndescent(points, n, d, z.gK, p->knn_seed, z.gRounds, g0, g0D, scratch, st,
+                               &rounds_run);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "nn-descent");
+        tg = now_ms();
+        e = cng::run_graph_candidates(points, n, d, g0, g0D, z.gK, entry_h, z.gL, z.Ceff, cand,
+                                      candD, scratch, st);
+        if (e != hipSuccess) return hip_fail(e, "graph candidates");
+        dtype = -1;
+    } else {
+        e = cng::launch_knn(points, n, points, n, d, z.Ceff, 1, z.knn, cand, candD, scratch, st, &ovf,
+                            &exact, &dtype);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "candidates");
+    }
     const double t2 = now_ms();
 
     e = cng::launch_prune(points, n, d, cand, candD, z.Ceff, p->R, z.W, p->alpha, p->tau, adj, st, 0,
@@ -218,6 +259,69 @@ cng_status cng_build(const float *points, int64_t n, int32_t d, const cng_build_
     S->overflow_rows = ovf;
     S->exact_integer = exact;
     S->filter_dtype = dtype;
+    S->ms_knn_graph = z.graph ? tg - t1 : 0.0;
+    S->knn_rounds_run = rounds_run;
+    return ok();
+}
+
+cng_status cng_nndescent_workspace_size(int64_t n, int32_t K, size_t *bytes)
+{
+    if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
+    if (n < 1 || n > MAX_N) return fail(CNG_EINVAL, "n out of range");
+    if (K < 1 || K > 64) return fail(CNG_EUNSUPPORTED, "K=%d must be in [1, 64]", K);
+    *bytes = cng::nndescent_workspace_bytes(n, K);
+    return ok();
+}
+
+cng_status cng_nndescent(const float *points, int64_t n, int32_t d, int32_t K, uint64_t seed,
+                         int32_t rounds, uint32_t *ids, float *D, void *workspace, size_t ws_bytes,
+                         void *stream, int32_t *rounds_host)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    size_t need = 0;
+    s = cng_nndescent_workspace_size(n, K, &need);
+    if (s != CNG_OK) return s;
+    if (rounds < 0) return fail(CNG_EINVAL, "rounds must be >= 0");
+    if (!ids || !D) return fail(CNG_EINVAL, "NULL array argument");
+    if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    int rr = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = cng::run_nndescent(points, n, d, K, seed, rounds, ids, D, workspace, st, &rr);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "nn-descent");
+    if (rounds_host) *rounds_host = rr;
+    return ok();
+}
+
+cng_status cng_graph_candidates_workspace_size(int64_t n, int32_t C, size_t *bytes)
+{
+    if (!bytes) return fail(CNG_EINVAL, "bytes is NULL");
+    if (n < 1 || n > MAX_N || C < 1) return fail(CNG_EINVAL, "n or C out of range");
+    *bytes = cng::graph_candidates_workspace_bytes(n, C);
+    return ok();
+}
+
+cng_status cng_graph_candidates(const float *points, int64_t n, int32_t d, const uint32_t *g0,
+                                const float *g0D, int32_t K, uint32_t entry, int32_t L, int32_t C,
+                                uint32_t *cand, float *candD, void *workspace, size_t ws_bytes,
+                                void *stream)
+{
+    cng_status s = check_points(points, n, d, 1);
+    if (s != CNG_OK) return s;
+    size_t need = 0;
+    s = cng_graph_candidates_workspace_size(n, C, &need);
+    if (s != CNG_OK) return s;
+    if (K < 1 || K > MAX_W) return fail(CNG_EINVAL, "K out of range");
+    if (L < 1) return fail(CNG_EINVAL, "L must be >= 1");
+    if (C + 1 + K > 256) return fail(CNG_EUNSUPPORTED, "C + 1 + K exceeds 256");
+    if ((L > C + 1 ? L : C + 1) > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "max(L, C + 1) exceeds %d", MAX_LEFF);
+    if ((int64_t)entry >= n) return fail(CNG_EINVAL, "entry %u >= n", entry);
+    if (!g0 || !g0D || !cand || !candD) return fail(CNG_EINVAL, "NULL array argument");
+    if (!workspace || ws_bytes < need) return fail(CNG_ENOMEM, "workspace too small");
+    hipError_t e = cng::run_graph_candidates(points, n, d, g0, g0D, K, entry, L, C, cand, candD,
+                                             workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "graph candidates");
     return ok();
 }
 

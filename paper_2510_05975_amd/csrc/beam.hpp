@@ -152,6 +152,58 @@ __device__ __forceinline__ void gather_dists(const void *__restrict__ vecs, cons
     }
 }
 
+// Merges the keys of the lanes with val set (distinct among themselves) into
+// the ascending list qa[0..qn) of at most cap entries: the union, cut to the
+// cap smallest (Algorithm 1's beam update).  A key equal to an entry is
+// dropped (an id that a forgetful visited table let through twice).  Explored
+// bits (bit 63) of the entries are kept and ignored in the order.  Returns the
+// new length.  tmp: 64 keys of LDS scratch.
+template <int QS>
+__device__ __forceinline__ int merge_keys(uint64_t *qa, int qn, int cap, uint64_t *tmp, uint64_t kc,
+                                          bool val)
+{
+    const int lane = lane_id();
+    if (qn == cap) val = val && kc < key_mask(qa[cap - 1]);
+    int lb = 0;
+    if (val) {
+        lb = lower_bound_keys(qa, qn, kc);
+        if (lb < qn && key_mask(qa[lb]) == kc) val = false;
+    }
+    const uint64_t sm = ballot(val);
+    const int ns = __popcll(sm);
+    if (ns == 0) return qn;
+    int rank = 0;
+    uint64_t it = sm;
+    while (it) {
+        const int j = __ffsll((unsigned long long)it) - 1;
+        it &= it - 1;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)kc, j);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(kc >> 32), j);
+        const uint64_t kj = ((uint64_t)hi << 32) | lo;
+        rank += kj < kc ? 1 : 0;
+    }
+    if (val) tmp[rank] = kc;
+    uint64_t old[QS];
+#pragma unroll
+    for (int j = 0; j < QS; ++j) {
+        const int e = j * 64 + lane;
+        old[j] = e < qn ? qa[e] : 0;
+    }
+    wave_sync();  // every old entry is in registers before any write
+    const int nqn = qn + ns < cap ? qn + ns : cap;
+#pragma unroll
+    for (int j = 0; j < QS; ++j) {
+        const int e = j * 64 + lane;
+        if (e < qn) {
+            const int np = e + lower_bound_keys(tmp, ns, key_mask(old[j]));
+            if (np < cap) qa[np] = old[j];
+        }
+    }
+    if (val && lb + rank < cap) qa[lb + rank] = kc;
+    wave_sync();
+    return nqn;
+}
+
 struct WaveLds {
     uint64_t *qa, *tmp;
     float *dsc;
@@ -262,49 +314,8 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
             wave_sync();
             ndc += (uint32_t)m;
             // ---- merge the m new keys into the beam (Algorithm 1: union, keep the L closest)
-            bool val = lane < m;
-            uint64_t kc = val ? make_key(s.dsc[lane], s.cid[lane]) : KEY_INF;
-            if (qn == Leff) val = val && kc < key_mask(qa[Leff - 1]);
-            int lb = 0;
-            if (val) {
-                lb = lower_bound_keys(qa, qn, kc);
-                // an id the visited table forgot may still be in the beam: same key, drop it
-                if (lb < qn && key_mask(qa[lb]) == kc) val = false;
-            }
-            uint64_t sm = ballot(val);
-            int ns = __popcll(sm);
-            if (ns > 0) {
-                int rank = 0;
-                uint64_t it = sm;
-                while (it) {
-                    int j = __ffsll((unsigned long long)it) - 1;
-                    it &= it - 1;
-                    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)kc, j);
-                    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(kc >> 32), j);
-                    uint64_t kj = ((uint64_t)hi << 32) | lo;
-                    rank += kj < kc ? 1 : 0;
-                }
-                if (val) s.tmp[rank] = kc;
-                uint64_t old[QS];
-#pragma unroll
-                for (int j = 0; j < QS; ++j) {
-                    int e = j * 64 + lane;
-                    old[j] = e < qn ? qa[e] : 0;
-                }
-                wave_sync();  // every old entry is in registers before any write
-                const int nqn = qn + ns < Leff ? qn + ns : Leff;
-#pragma unroll
-                for (int j = 0; j < QS; ++j) {
-                    int e = j * 64 + lane;
-                    if (e < qn) {
-                        int np = e + lower_bound_keys(s.tmp, ns, key_mask(old[j]));
-                        if (np < Leff) qa[np] = old[j];
-                    }
-                }
-                if (val && lb + rank < Leff) qa[lb + rank] = kc;
-                wave_sync();
-                qn = nqn;
-            }
+            const uint64_t kc = lane < m ? make_key(s.dsc[lane], s.cid[lane]) : KEY_INF;
+            qn = merge_keys<QS>(qa, qn, Leff, s.tmp, kc, lane < m);
             if (cut < 64) break;
         }
     }
@@ -333,7 +344,7 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
         if (e < qn) {
             uint64_t ke = qa[e];
             id = key_id(ke);
-            dist = __builtin_sqrtf(key_dist(ke));
+            dist = a.out_sq ? key_dist(ke) : __builtin_sqrtf(key_dist(ke));
         }
         a.ids[(size_t)qi * a.k + e] = id;
         a.dists[(size_t)qi * a.k + e] = dist;

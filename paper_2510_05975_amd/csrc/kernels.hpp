@@ -26,6 +26,7 @@ struct SearchArgs {
     float *dists;
     uint32_t *hops, *ndc;
     int vlog2;
+    int out_sq;                // dists receive the squared distances D instead of sqrt(D)
 };
 
 hipError_t launch_search(const SearchArgs &a, hipStream_t stream);
@@ -91,6 +92,15 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band, int64_t pass_ro
 hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t nc, int d, int C,
                       int exclude_self, const KnnPlan &plan, uint32_t *ids, float *D, void *ws,
                       hipStream_t stream, int64_t *overflow_rows, int *exact_int, int *dtype);
+
+// sub-quadratic candidates: NN-descent K-NN graph and a beam search on it
+size_t nndescent_workspace_bytes(int64_t n, int K);
+hipError_t run_nndescent(const float *points, int64_t n, int d, int K, uint64_t seed, int rounds,
+                         uint32_t *ids, float *D, void *ws, hipStream_t st, int *rounds_run);
+size_t graph_candidates_workspace_bytes(int64_t n, int C);
+hipError_t run_graph_candidates(const float *points, int64_t n, int d, const uint32_t *g0,
+                                const float *g0D, int K, uint32_t s_host, int L, int C,
+                                uint32_t *cand, float *candD, void *ws, hipStream_t st);
 
 // pruning; with copy_upto > 0 a list of at most copy_upto candidates becomes
 // the row unpruned; alpha_step > 0: adaptive alpha (Algorithm 4) from alpha to

@@ -14,8 +14,7 @@
 
 #include <cmath>
 
-#include "common.hpp"
-#include "kernels.hpp"
+#include "beam.hpp"
 
 namespace cng {
 
@@ -48,6 +47,28 @@ __device__ __forceinline__ double dist_f64_group(const float *__restrict__ x,
     return group_sum_f64<G>(acc);
 }
 
+// Lazy pruning (Section 4.3): with copy_upto > 0 a list of at most copy_upto
+// candidates becomes point p's row as it is.  Returns true if it did.
+__device__ __forceinline__ bool copy_short_list(const PruneArgs &a, int64_t p)
+{
+    if (!(a.copy_upto > 0 &&
+          (a.C <= a.copy_upto || a.cand[(size_t)p * a.C + a.copy_upto] == NONE)))
+        return false;
+    const int lane = lane_id();
+    uint32_t *out = a.adj + (size_t)p * a.W;
+    bool alive = true;
+    for (int s0 = 0; s0 < a.W; s0 += 64) {
+        const int s = s0 + lane;
+        uint32_t u = s < a.C && s < a.copy_upto ? a.cand[(size_t)p * a.C + s] : NONE;
+        const bool ok = alive && u != NONE && (int64_t)u < a.n;
+        const uint64_t bad = ballot(!ok);
+        const int first_bad = bad ? __builtin_ctzll(bad) : 64;
+        if (s < a.W) out[s] = ok && lane < first_bad ? u : NONE;
+        if (bad) alive = false;
+    }
+    return true;
+}
+
 template <int G, int RND, bool VEC, int UB>
 __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
 {
@@ -62,22 +83,7 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
     uint32_t *S = reinterpret_cast<uint32_t *>(smem) + (size_t)wave * a.R;
     const int d = a.d;
 
-    if (a.copy_upto > 0 &&
-        (a.C <= a.copy_upto || a.cand[(size_t)p * a.C + a.copy_upto] == NONE)) {
-        // short list: it becomes the row as it is (lazy pruning, Section 4.3)
-        uint32_t *out = a.adj + (size_t)p * a.W;
-        bool alive = true;
-        for (int s0 = 0; s0 < a.W; s0 += 64) {
-            const int s = s0 + lane;
-            uint32_t u = s < a.C && s < a.copy_upto ? a.cand[(size_t)p * a.C + s] : NONE;
-            const bool ok = alive && u != NONE && (int64_t)u < a.n;
-            const uint64_t bad = ballot(!ok);
-            const int first_bad = bad ? __builtin_ctzll(bad) : 64;
-            if (s < a.W) out[s] = ok && lane < first_bad ? u : NONE;
-            if (bad) alive = false;
-        }
-        return;
-    }
+    if (copy_short_list(a, p)) return;
     const float ta = (float)a.tau;
     const float *xp = a.points + (size_t)p * d;
 
@@ -153,6 +159,169 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
     for (int s = lane; s < a.W; s += 64) out[s] = s < ns ? S[s] : NONE;
 }
 
+// Algorithm 4 with the distance reuse of Section 4.3: the alpha passes run one
+// after the other as in prune_kernel, but the distance of a pair (u, v) of
+// candidates is kept in an LDS table (keyed by the two list positions) once
+// evaluated, so each pair is computed once across the passes: a later pass
+// only looks its pairs up.  Per candidate u the kept points are taken in
+// batches of 64 pairs: cached pairs are decided first (u may be pruned without
+// computing anything), the missing distances are then computed G lanes per
+// pair (gather_dists, the fixed order) and entered in the table.  Every
+// decision is the comparison of prune_kernel on the same float32 distance
+// (near-ties re-decided from float64 distances, by the whole wave), so the
+// kept sets are those of running each pass alone.  The table may forget
+// (bounded probing, overwrite): a forgotten pair is computed again, to the
+// same bits.
+constexpr int MAX_PASSES = 1024;
+constexpr int PAIR_LOG2 = 10;  // table slots per wave
+
+__host__ __device__ constexpr size_t adaptive_lds_per_wave(int R)
+{
+    // the table (key << 32 | distance bits), a batch's ids and distances, kept
+    // ids and positions
+    return ((size_t)8 << PAIR_LOG2) + 64 * 8 + (size_t)R * 8;
+}
+
+__device__ __forceinline__ uint32_t pair_slot(uint32_t key, int t)
+{
+    return ((key * 0x9E3779B1u) >> (32 - PAIR_LOG2)) + (uint32_t)t & ((1u << PAIR_LOG2) - 1u);
+}
+
+template <int G, int RND, bool VEC, int UB>
+__global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int gl = lane % G;
+    const int64_t p = (int64_t)blockIdx.x * wpb + wave;
+    if (p >= a.n) return;
+    if (copy_short_list(a, p)) return;
+    unsigned char *base = smem + (size_t)wave * adaptive_lds_per_wave(a.R);
+    // table entries hold key << 32 | float bits of the distance, so that an
+    // entry is written whole (one 64-bit store or atomic)
+    unsigned long long *tab = reinterpret_cast<unsigned long long *>(base);  // [2^PAIR_LOG2]
+    uint32_t *cid = reinterpret_cast<uint32_t *>(tab + (1 << PAIR_LOG2));  // [64]
+    float *dsc = reinterpret_cast<float *>(cid + 64);               // [64]
+    uint32_t *Sid = reinterpret_cast<uint32_t *>(dsc + 64);         // [R]
+    uint32_t *Spos = Sid + a.R;                                     // [R]
+    const int d = a.d;
+    constexpr unsigned long long EMPTY = ~0ull;
+    for (int i = lane; i < (1 << PAIR_LOG2); i += 64) tab[i] = EMPTY;
+    wave_sync();
+    const float ta = (float)a.tau;
+    const float *xp = a.points + (size_t)p * d;
+    const uint32_t *cand = a.cand + (size_t)p * a.C;
+
+    int ns = 0;
+    for (int it = 0; it < a.iters; ++it) {
+        const double alpha = a.alpha + it * a.alpha_step;
+        const float al = (float)alpha;
+        const float cterm = (al + 1.0f) * ta;
+        ns = 0;
+        for (int j = 0; j < a.C && ns < a.R; ++j) {
+            const uint32_t u = cand[j];
+            if (u == NONE || (int64_t)u >= a.n) break;
+            const float lhs = __builtin_sqrtf(a.candD[(size_t)p * a.C + j]);
+            const float band = 1e-6f * lhs;
+            const float *xu = a.points + (size_t)u * d;
+            bool have_u = false;
+            float4 ur[RND];
+            bool pruned = false;
+            for (int b = 0; b < ns && !pruned; b += 64) {
+                const int t = b + lane;
+                const bool valid = t < ns;
+                // look the pair (j, position of kept point t) up
+                const uint32_t key = valid ? ((uint32_t)j << 16) | Spos[t] : NONE;
+                float bd = 0.f;
+                bool hit = false;
+                if (valid) {
+                    for (int q = 0; q < 8; ++q) {
+                        const unsigned long long e = tab[pair_slot(key, q)];
+                        if ((uint32_t)(e >> 32) == key) {
+                            bd = __uint_as_float((uint32_t)e);
+                            hit = true;
+                            break;
+                        }
+                        if (e == EMPTY) break;
+                    }
+                }
+                // decisions of the cached pairs (float32 unless near a tie)
+                bool tie = false, dec = false;
+                if (hit) {
+                    const float rhs = al * bd + cterm;
+                    tie = __builtin_fabsf(lhs - rhs) <= band;
+                    dec = !tie && lhs > rhs;
+                }
+                if (ballot(dec)) {
+                    pruned = true;
+                    break;
+                }
+                // the missing distances, G lanes per pair
+                const bool miss = valid && !hit;
+                const uint64_t mm = ballot(miss);
+                const int m = __popcll(mm);
+                if (m > 0) {
+                    if (!have_u) {
+#pragma unroll
+                        for (int r = 0; r < RND; ++r) ur[r] = load_chunk<VEC>(xu, d, r, gl);
+                        have_u = true;
+                    }
+                    const int slot = __popcll(mm & ((1ull << lane) - 1ull));
+                    if (miss) cid[slot] = Sid[t];
+                    wave_sync();
+                    beam::gather_dists<G, RND, VEC, UB, 0>(a.points, nullptr, d, cid, m, ur, dsc);
+                    wave_sync();
+                    if (miss) {
+                        bd = __builtin_sqrtf(dsc[slot]);
+                        // enter it (overwrite the home slot when the probes are full)
+                        const unsigned long long ent = ((unsigned long long)key << 32) | __float_as_uint(bd);
+                        bool placed = false;
+                        for (int q = 0; q < 8 && !placed; ++q) {
+                            const unsigned long long old = atomicCAS(&tab[pair_slot(key, q)], EMPTY, ent);
+                            placed = old == EMPTY || (uint32_t)(old >> 32) == key;
+                        }
+                        if (!placed) atomicExch(&tab[pair_slot(key, 0)], ent);
+                        const float rhs = al * bd + cterm;
+                        tie = __builtin_fabsf(lhs - rhs) <= band;
+                        dec = !tie && lhs > rhs;
+                    }
+                    wave_sync();
+                    if (ballot(dec)) {
+                        pruned = true;
+                        break;
+                    }
+                }
+                // near-ties: re-decided from float64 distances, one pair at a
+                // time by the whole wave
+                uint64_t tm = ballot(tie);
+                while (tm && !pruned) {
+                    const int l = __builtin_ctzll(tm);
+                    tm &= tm - 1;
+                    const uint32_t v = Sid[b + l];
+                    const float *xv = a.points + (size_t)v * d;
+                    const double a64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xp, xu, d, gl));
+                    const double b64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xu, xv, d, gl));
+                    pruned = a64 > alpha * b64 + (alpha + 1.0) * a.tau;
+                }
+            }
+            if (!pruned) {
+                wave_sync();
+                if (lane == 0) {
+                    Sid[ns] = u;
+                    Spos[ns] = (uint32_t)j;
+                }
+                wave_sync();
+                ++ns;
+            }
+        }
+        if (2 * ns >= a.R) break;
+    }
+    uint32_t *out = a.adj + (size_t)p * a.W;
+    for (int s2 = lane; s2 < a.W; s2 += 64) out[s2] = s2 < ns ? Sid[s2] : NONE;
+}
+
 using PruneFn = void (*)(PruneArgs);
 
 template <int G, int RND, bool VEC>
@@ -160,6 +329,27 @@ PruneFn prune_fn()
 {
     constexpr int UB = G == 32 ? (RND >= 8 ? 1 : 8 / RND) : 4;
     return prune_kernel<G, RND, VEC, UB>;
+}
+
+template <int G, int RND, bool VEC>
+PruneFn adaptive_fn()
+{
+    constexpr int UB = G == 32 ? (RND >= 8 ? 1 : 8 / RND) : 4;
+    return prune_adaptive_kernel<G, RND, VEC, UB>;
+}
+
+template <bool VEC>
+PruneFn pick_adaptive(int d)
+{
+    if (d <= 32) return adaptive_fn<8, 1, VEC>();
+    if (d <= 64) return adaptive_fn<16, 1, VEC>();
+    int rnd = (d + 127) / 128;
+    if (rnd <= 1) return adaptive_fn<32, 1, VEC>();
+    if (rnd <= 2) return adaptive_fn<32, 2, VEC>();
+    if (rnd <= 4) return adaptive_fn<32, 4, VEC>();
+    if (rnd <= 8) return adaptive_fn<32, 8, VEC>();
+    if (rnd <= 16) return adaptive_fn<32, 16, VEC>();
+    return adaptive_fn<32, 32, VEC>();
 }
 
 template <bool VEC>
@@ -194,9 +384,15 @@ hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *c
     PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj, copy_upto, iters,
                 alpha_step};
     const bool vec = (d % 4 == 0) && ((uintptr_t)points % 16 == 0);
-    PruneFn fn = vec ? pick_prune<true>(d) : pick_prune<false>(d);
     const int wpb = 4;
     const int64_t blocks = (n + wpb - 1) / wpb;
+    if (iters > 1 && iters <= MAX_PASSES) {
+        PruneFn fn = vec ? pick_adaptive<true>(d) : pick_adaptive<false>(d);
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb),
+                           (unsigned)(wpb * adaptive_lds_per_wave(R)), stream, a);
+        return hipGetLastError();
+    }
+    PruneFn fn = vec ? pick_prune<true>(d) : pick_prune<false>(d);
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), (unsigned)(wpb * R * 4), stream, a);
     return hipGetLastError();
 }

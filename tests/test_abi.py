@@ -19,7 +19,8 @@ def test_exports_every_declared_symbol():
 
 def _params(**kw):
     p = dict(R=32, extra=1, C=128, alpha=1.2, tau=0.0, flags=1, Lc=0, band=0, visited_log2=0,
-             alpha_max=1.2, alpha_step=0.0, pass_rows=0)
+             alpha_max=1.2, alpha_step=0.0, pass_rows=0, knn_K=0, knn_rounds=0, cand_L=0,
+             knn_seed=0)
     p.update(kw)
     return _lib.BuildParams(*[p[f] for f, _ in _lib.BuildParams._fields_])
 

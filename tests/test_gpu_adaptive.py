@@ -35,6 +35,19 @@ def test_prune_adaptive(case):
     assert (host_ids(got) == want).all()
 
 
+@pytest.mark.parametrize("step,R", [(0.02, 15), (0.01, 16)])
+def test_prune_adaptive_many_passes(step, R):
+    """36 passes (all alpha passes in one sweep) and 71 passes (more than the
+    sweep holds: one pass after the other), odd and even R."""
+    x, _ = workloads.generate(1, n=3000, nq=1)
+    cand, D = oracle.knn(x, x, 48, exclude_self=True)
+    want = oracle.prune(x, cand, D, R, A0, width=R + 1, alpha_max=AMAX, alpha_step=step)
+    got = cng.prune(dev(x), dev_ids(cand), dev(f32_of(D)), R, A0, 0.0, width=R + 1,
+                    alpha_max=AMAX, alpha_step=step)
+    torch.cuda.synchronize()
+    assert (host_ids(got) == want).all()
+
+
 def test_prune_adaptive_hand_worked():
     g = json.load(open(os.path.join(GOLD, "adaptive_alpha.json")))
     for case in g["cases"]:
