@@ -364,6 +364,23 @@ cng_status cng_entry_predict(const float *params, int32_t d, int32_t H, int32_t 
                              uint32_t *out_entry, float *out_conf, void *workspace,
                              size_t workspace_bytes, void *stream);
 
+/* cng_entry_predict without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Its scratch memory is a fixed device
+ * array of cng_entry_predict_noalloc_max_bytes() bytes (16 MiB) that the
+ * library holds on every GPU it runs on until the process ends; the call
+ * allocates nothing.  Shapes whose scratch (cng_mlp_workspace_size(d, H, K,
+ * B)) exceeds it are refused with CNG_EUNSUPPORTED.  Every call on one GPU
+ * uses that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race; calls in order on one stream do not.  Nothing in the array
+ * needs to start at zero.  Outputs and arguments as cng_entry_predict. */
+size_t cng_entry_predict_noalloc_max_bytes(void);
+cng_status cng_entry_predict_noalloc(const float *params, int32_t d, int32_t H, int32_t K,
+                                     const float *X, const float *x_mean, const float *x_scale,
+                                     int32_t B, int32_t precision, const uint32_t *entries,
+                                     uint32_t fallback, float theta, uint32_t *out_entry,
+                                     float *out_conf, void *stream);
+
 /* Ablation baseline without a network: entries[index of the nearest centre]. */
 size_t cng_nearest_centre_workspace_size(int64_t nq, int32_t d, int32_t K);
 cng_status cng_nearest_centre_entry(const float *queries, int64_t nq, int32_t d, const float *centers,

@@ -106,6 +106,9 @@ _SIGS = {
     "cng_mlp_logits": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, sz, vp]),
     "cng_entry_predict": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, i32, i32, vp, u32, C.c_float, vp,
                                     vp, vp, sz, vp]),
+    "cng_entry_predict_noalloc_max_bytes": (sz, []),
+    "cng_entry_predict_noalloc": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, i32, i32, vp, u32,
+                                            C.c_float, vp, vp, vp]),
     "cng_nearest_centre_workspace_size": (sz, [i64, i32, i32]),
     "cng_nearest_centre_entry": (C.c_int, [vp, i64, i32, vp, i32, vp, vp, vp, sz, vp]),
     "cng_serve_workspace_size": (sz, []),
@@ -497,6 +500,22 @@ def entry_predict(params, d, H, K, X, precision, entries, fallback: int, theta: 
                                                         _ptr(out), _ptr(conf), _ptr(ws), nb,
                                                         _stream()))
     return out, conf
+
+
+def entry_predict_noalloc(params, d, H, K, X, precision, entries, fallback: int, theta: float,
+                          affine=None, out=None):
+    """cng_entry_predict_noalloc (the library's fixed scratch array, no
+    workspace): out = (entries int32 [B], conf float32 [B]) or new tensors."""
+    X = _f32(X)
+    xm, xs = affine if affine is not None else (None, None)
+    B = X.shape[0]
+    if out is None:
+        out = (torch.empty(B, dtype=torch.int32, device=X.device),
+               torch.empty(B, dtype=torch.float32, device=X.device))
+    _check("cng_entry_predict_noalloc", lib().cng_entry_predict_noalloc(
+        _ptr(params), d, H, K, _ptr(X), _ptr(xm), _ptr(xs), B, precision, _ptr(_ids(entries)),
+        fallback, theta, _ptr(out[0]), _ptr(out[1]), _stream()))
+    return out
 
 
 def nearest_centre_entry(queries, centers, entries):

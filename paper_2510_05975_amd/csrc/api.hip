@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstdarg>
 #include <cstring>
@@ -714,6 +715,69 @@ cng_status cng_entry_predict(const float *params, int32_t d, int32_t H, int32_t 
                                     (float *)workspace, out_entry, out_conf, (hipStream_t)stream,
                                     x_mean, x_scale);
     if (e != hipSuccess) return hip_fail(e, "entry predict");
+    return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free prediction
+// A fixed device array holds the scratch memory of cng_entry_predict_noalloc.
+// In host code `scratch` only names the symbol: its device address, one per
+// GPU, comes from hipGetSymbolAddress on the first call on that device (with
+// that device current) and is kept in scratch_ptr.
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static cng_status device_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(CNG_EUNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return CNG_OK;
+}
+
+extern "C" {
+
+size_t cng_entry_predict_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+cng_status cng_entry_predict_noalloc(const float *params, int32_t d, int32_t H, int32_t K,
+                                     const float *X, const float *x_mean, const float *x_scale,
+                                     int32_t B, int32_t precision, const uint32_t *entries,
+                                     uint32_t fallback, float theta, uint32_t *out_entry,
+                                     float *out_conf, void *stream)
+{
+    cng_status s = check_mlp(d, H, K, B, precision);
+    if (s != CNG_OK) return s;
+    s = check_affine(x_mean, x_scale);
+    if (s != CNG_OK) return s;
+    if (!params || !X || !entries || !out_entry) return fail(CNG_EINVAL, "NULL array argument");
+    cng::MlpShape sh(d, H, K);
+    const size_t need = cng::mlp_workspace_floats(sh, B) * 4;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(CNG_EUNSUPPORTED, "scratch of %zu bytes needed, the static array holds %zu", need,
+                    NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    s = device_scratch(&ws);
+    if (s != CNG_OK) return s;
+    hipError_t e = cng::mlp_predict(sh, params, X, B, precision == 1, entries, fallback, theta,
+                                    (float *)ws, out_entry, out_conf, (hipStream_t)stream, x_mean,
+                                    x_scale);
+    if (e != hipSuccess) return hip_fail(e, "entry predict (no allocation)");
     return ok();
 }
 
