@@ -175,11 +175,11 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
 constexpr int MAX_PASSES = 1024;
 constexpr int PAIR_LOG2 = 10;  // table slots per wave
 
-__host__ __device__ constexpr size_t adaptive_lds_per_wave(int R)
+__host__ __device__ constexpr size_t adaptive_lds_per_wave(int R, int C)
 {
     // the table (key << 32 | distance bits), a batch's ids and distances, kept
-    // ids and positions
-    return ((size_t)8 << PAIR_LOG2) + 64 * 8 + (size_t)R * 8;
+    // ids and positions, the candidate list (ids and distances)
+    return ((size_t)8 << PAIR_LOG2) + 64 * 8 + (size_t)R * 8 + (size_t)C * 8;
 }
 
 __device__ __forceinline__ uint32_t pair_slot(uint32_t key, int t)
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
     const int64_t p = (int64_t)blockIdx.x * wpb + wave;
     if (p >= a.n) return;
     if (copy_short_list(a, p)) return;
-    unsigned char *base = smem + (size_t)wave * adaptive_lds_per_wave(a.R);
+    unsigned char *base = smem + (size_t)wave * adaptive_lds_per_wave(a.R, a.C);
     // table entries hold key << 32 | float bits of the distance, so that an
     // entry is written whole (one 64-bit store or atomic)
     unsigned long long *tab = reinterpret_cast<unsigned long long *>(base);  // [2^PAIR_LOG2]
@@ -206,13 +206,19 @@ __global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
     float *dsc = reinterpret_cast<float *>(cid + 64);               // [64]
     uint32_t *Sid = reinterpret_cast<uint32_t *>(dsc + 64);         // [R]
     uint32_t *Spos = Sid + a.R;                                     // [R]
+    uint32_t *cand = Spos + a.R;                                    // [C] this point's list
+    float *lhsv = reinterpret_cast<float *>(cand + a.C);            // [C] its sqrt(D(p, u))
     const int d = a.d;
     constexpr unsigned long long EMPTY = ~0ull;
     for (int i = lane; i < (1 << PAIR_LOG2); i += 64) tab[i] = EMPTY;
+    // the candidate list, read once for all passes
+    for (int j = lane; j < a.C; j += 64) {
+        cand[j] = a.cand[(size_t)p * a.C + j];
+        lhsv[j] = __builtin_sqrtf(a.candD[(size_t)p * a.C + j]);
+    }
     wave_sync();
     const float ta = (float)a.tau;
     const float *xp = a.points + (size_t)p * d;
-    const uint32_t *cand = a.cand + (size_t)p * a.C;
 
     int ns = 0;
     for (int it = 0; it < a.iters; ++it) {
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
         for (int j = 0; j < a.C && ns < a.R; ++j) {
             const uint32_t u = cand[j];
             if (u == NONE || (int64_t)u >= a.n) break;
-            const float lhs = __builtin_sqrtf(a.candD[(size_t)p * a.C + j]);
+            const float lhs = lhsv[j];
             const float band = 1e-6f * lhs;
             const float *xu = a.points + (size_t)u * d;
             bool have_u = false;
@@ -384,14 +390,18 @@ hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *c
     PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj, copy_upto, iters,
                 alpha_step};
     const bool vec = (d % 4 == 0) && ((uintptr_t)points % 16 == 0);
-    const int wpb = 4;
-    const int64_t blocks = (n + wpb - 1) / wpb;
-    if (iters > 1 && iters <= MAX_PASSES) {
+    const size_t lds_wave = adaptive_lds_per_wave(R, C);
+    if (iters > 1 && iters <= MAX_PASSES && lds_wave <= 64 * 1024) {
+        // as many waves per workgroup (up to 4) as 64 KB of LDS holds
+        int wpa = 4;
+        while (wpa > 1 && (size_t)wpa * lds_wave > 64 * 1024) wpa >>= 1;
         PruneFn fn = vec ? pick_adaptive<true>(d) : pick_adaptive<false>(d);
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb),
-                           (unsigned)(wpb * adaptive_lds_per_wave(R)), stream, a);
+        hipLaunchKernelGGL(fn, dim3((unsigned)((n + wpa - 1) / wpa)), dim3(64 * wpa),
+                           (unsigned)(wpa * lds_wave), stream, a);
         return hipGetLastError();
     }
+    const int wpb = 4;
+    const int64_t blocks = (n + wpb - 1) / wpb;
     PruneFn fn = vec ? pick_prune<true>(d) : pick_prune<false>(d);
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), (unsigned)(wpb * R * 4), stream, a);
     return hipGetLastError();
