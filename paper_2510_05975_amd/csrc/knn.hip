@@ -153,21 +153,30 @@ struct FilterArgs {
     uint32_t *bandI;
     int *cnt;        // [chunk]; -1 = overflowed
     PrepOut *st;
-    // bf16 filters: > 0 starts a workgroup's column sweep this many columns
-    // before the middle of its rows (self-joins in locality order, where the
-    // nearest columns of a row sit around its own position) and wraps around
-    int64_t back;
+    // bf16 filters, self-joins in locality order (nullable): the end of each of
+    // the ncells cells in the order (cell c spans cell_ends[c - 1] ..
+    // cell_ends[c]).  A workgroup then starts its column sweep at the first
+    // tile of the cell holding its middle row, where the nearest columns of
+    // its rows are, and wraps around.
+    const uint32_t *cell_ends;
+    int ncells;
 };
 
-// First column tile of a workgroup's sweep (see FilterArgs::back).
+// First column tile of a workgroup's sweep (see FilterArgs::cell_ends).
 __device__ __forceinline__ int64_t first_tile(const FilterArgs &a, int64_t row0, int rows, int bn)
 {
-    const int64_t ntiles = (a.nc + bn - 1) / bn;
-    if (a.back <= 0) return 0;
-    int64_t c = row0 + rows / 2 - a.back;
-    int64_t t = c >= 0 ? c / bn : -((-c + bn - 1) / bn);
-    t %= ntiles;
-    return t < 0 ? t + ntiles : t;
+    if (!a.cell_ends) return 0;
+    int64_t mid = row0 + rows / 2;
+    if (mid > a.nc - 1) mid = a.nc - 1;
+    // the cell of mid: the first c with cell_ends[c] > mid
+    int lo = 0, hi = a.ncells - 1;
+    while (lo < hi) {
+        const int md = (lo + hi) / 2;
+        if ((int64_t)a.cell_ends[md] > mid) hi = md;
+        else lo = md + 1;
+    }
+    const int64_t start = lo > 0 ? (int64_t)a.cell_ends[lo - 1] : 0;
+    return start / bn;
 }
 
 struct FilterLds {
@@ -1206,7 +1215,7 @@ __global__ __launch_bounds__(256) void exhaustive_kernel(RerankArgs a, int exclu
 // Self-joins (d <= 128) sweep their columns in an order where a row's nearest
 // columns sit near its own position: every point goes to the cell of its nearest sample
 // point (K samples at evenly spaced ids), points are grouped by cell (in any
-// order within a cell), and a workgroup starts its sweep around its own rows.
+// order within a cell), and a workgroup starts its sweep at its own cell.
 // The thresholds of its rows then settle within the first tiles instead of
 // over the whole sweep, which saves band appends and compactions.  The
 // candidate lists do not depend on the order: the band rule holds for any
@@ -1338,16 +1347,18 @@ size_t filter_lds_bytes(int CB)
 }  // namespace
 
 // Locality order of self-joins: from this many points on, for d <= 128, with
-// about 1024 points per cell, and sweeps that start this many columns before a
-// workgroup's rows (about half a cell).  Measured on the 1M x 128 integer
-// workload: 2430 band appends and 6.5 compactions per row without the order,
-// 1530 and 3.7 with it (candidate stage 0.51 -> 0.46 s); cells of 4096 to
-// 16384 points gain nothing more (a row's 128 nearest neighbours reach far
-// beyond its cell in this intrinsic dimension), and at d = 960 the order does
-// not pay for itself.
+// about 1024 points per cell.  Measured on the 1M x 128 integer workload: 2430
+// band appends and 6.5 compactions per row without the order, 1530 and 3.7
+// with it (candidate stage 0.51 -> 0.46 s); cells of 4096 to 16384 points gain
+// nothing more (a row's 128 nearest neighbours reach far beyond its cell in
+// this intrinsic dimension), and at d = 960 the order does not pay for itself.
+// Sweeps start at the first tile of the workgroup's cell: 0.437 -> 0.419 s
+// against a start half a cell before the workgroup's rows (which often lies in
+// the previous cell, an unrelated one); sweeping the tiles of the 6, 12 or 24
+// cells with the nearest sample points first instead gained nothing more
+// (0.417, 0.434, 0.437 s).
 constexpr int64_t ORDER_MIN = 2048;
 constexpr int ORDER_MAX_D = 128;
-constexpr int64_t ORDER_BACK = 512;
 
 int order_cells(int64_t n)
 {
@@ -1464,7 +1475,7 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
 
     // locality order of a self-join (bf16 filters only)
     const bool ordered = self && plan.order_K > 0 && (use_bf16 || use_split);
-    const uint32_t *ord = nullptr;
+    const uint32_t *ord = nullptr, *cell_ends = nullptr;
     const float *Ef = E, *nyf = ny;
     if (ordered) {
         const int K = plan.order_K;
@@ -1502,6 +1513,7 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
         hipLaunchKernelGGL(gather_f32, dim3(gn), dim3(256), 0, stream, E, order, nr, Ep);
         hipLaunchKernelGGL(gather_f32, dim3(gn), dim3(256), 0, stream, ny, order, nr, nyp);
         ord = order;
+        cell_ends = cursor;  // after the scatter, cursor[c] is the end of cell c
         Ef = Ep;
         nyf = nyp;
     }
@@ -1536,7 +1548,7 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     for (int64_t r0 = 0; r0 < nr; r0 += plan.chunk_rows) {
         const int64_t chunk = nr - r0 < plan.chunk_rows ? nr - r0 : plan.chunk_rows;
         FilterArgs fa{rows, nr, r0, chunk, cols, nc, d, C, exclude_self, nyf, Ef, CB, bandF, bandI, cnt, st,
-                      ordered ? ORDER_BACK : 0};
+                      cell_ends, ordered ? plan.order_K : 0};
         if ((use_bf16 || use_split) && wide) {
             FilterBf16Args fb{fa, rows16, cols16, rows16lo, cols16lo};
             const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
