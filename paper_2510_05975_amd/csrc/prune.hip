@@ -10,6 +10,11 @@
 // is re-decided from float64 distances of the same reduction order.  At most R
 // candidates are kept (stopping there equals keeping the R closest of the full
 // shortcut set, since a decision only looks at earlier kept points).
+// Three kernels make the same decisions: prune_reg_kernel (d <= 128, R <= 32,
+// C <= 128: kept vectors in registers; 1M x 128, R = 32: 11 ms against 33 ms
+// for prune_kernel, adaptive alpha 0.9 .. 1.6: 92 ms against 192 ms for the
+// table kernel), prune_kernel (fixed alpha otherwise) and
+// prune_adaptive_kernel (adaptive alpha otherwise).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -328,6 +333,184 @@ __global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
     for (int s2 = lane; s2 < a.W; s2 += 64) out[s2] = s2 < ns ? Sid[s2] : NONE;
 }
 
+// Fixed and adaptive pruning with the kept points' vectors in registers: for
+// d <= 128 (float4 chunks, 32 lanes per vector), R <= 32 and C <= 128.  Lane
+// group g (lanes 32g .. 32g+31) holds kept points 2q + g in kv[q], so a
+// candidate u is compared with every kept point by one chunk product per kept
+// pair per lane and one recursive-halving reduction (group_sums: each sum is
+// the fixed-order butterfly of one pair, bit for bit; with d <= 64 the upper
+// lanes add exact zeros).  Only the candidate vectors are read from memory, a
+// block of REG_AHEAD candidates ahead.  Decisions are those of prune_kernel:
+// float32 unless near a tie, then float64 (from the registers).  The passes of
+// Algorithm 4 run one after the other and recompute their pairs: evaluating
+// several alpha values in one sweep over a shared set of kept vectors (the
+// union of the passes' kept sets) was measured slower, its union outgrowing
+// the registers of one wave (1M x 128: 144 ms for pairs of passes, 192 ms for
+// fours, 95 ms one at a time).
+constexpr int REG_KEPT = 32, REG_CAND = 128, REG_AHEAD = 2;
+
+// Squared distances of candidate u (chunk ur) to the kept points 2q + g, q <
+// UB: on return the lanes gl % (32 / UB) == 0 of group g hold kept point
+// 2 * (gl / (32 / UB)) + g.
+template <int UB>
+__device__ __forceinline__ float reg_sums(const float4 &ur, const float4 (&kv)[REG_KEPT / 2], int gl)
+{
+    float acc[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) acc[q] = chunk_fma(ur, kv[q], 0.f);
+    group_sums<32, UB>(acc, gl);
+    return acc[0];
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void prune_reg_kernel(PruneArgs a)
+{
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int g = lane >> 5, gl = lane & 31;
+    const int64_t p = (int64_t)blockIdx.x * wpb + wave;
+    if (p >= a.n) return;
+    if (copy_short_list(a, p)) return;
+    const int d = a.d;
+    const float ta = (float)a.tau;
+    // the candidate list in registers: lane l holds entries l and l + 64, with
+    // sqrt(D(p, u)); the list ends at its first invalid entry
+    const uint32_t *cl = a.cand + (size_t)p * a.C;
+    const float *cd = a.candD + (size_t)p * a.C;
+    const uint32_t c0 = lane < a.C ? cl[lane] : NONE;
+    const uint32_t c1 = lane + 64 < a.C ? cl[lane + 64] : NONE;
+    const float l0 = lane < a.C ? __builtin_sqrtf(cd[lane]) : 0.f;
+    const float l1 = lane + 64 < a.C ? __builtin_sqrtf(cd[lane + 64]) : 0.f;
+    int len;
+    {
+        const uint64_t b0 = ballot(!(c0 != NONE && (int64_t)c0 < a.n));
+        const uint64_t b1 = ballot(!(c1 != NONE && (int64_t)c1 < a.n));
+        len = b0 ? __builtin_ctzll(b0) : 64 + (b1 ? __builtin_ctzll(b1) : 64);
+        if (len > a.C) len = a.C;
+    }
+    auto cand_at = [&](int j) -> uint32_t {
+        return (uint32_t)(j < 64 ? __builtin_amdgcn_readlane((int)c0, j)
+                                 : __builtin_amdgcn_readlane((int)c1, j - 64));
+    };
+    auto lhs_at = [&](int j) -> float {
+        return __int_as_float(j < 64 ? __builtin_amdgcn_readlane(__float_as_int(l0), j)
+                                     : __builtin_amdgcn_readlane(__float_as_int(l1), j - 64));
+    };
+    // Lane gl's chunk of a row, loaded unconditionally (lanes past d read the
+    // row's first chunk and mask it when it is used): no load sits in a
+    // divergent branch, so a use waits for its own loads only.
+    const bool in_d = gl * 4 < d;
+    auto raw_chunk = [&](uint32_t id) -> float4 {
+        return *reinterpret_cast<const float4 *>(a.points + (size_t)id * d + (in_d ? gl * 4 : 0));
+    };
+    auto masked = [&](float4 v) -> float4 { return in_d ? v : make_float4(0.f, 0.f, 0.f, 0.f); };
+    // candidate j's chunk; past the list, point p's own (a valid row)
+    auto fetch = [&](int j) -> float4 { return raw_chunk(j < len ? cand_at(j) : (uint32_t)p); };
+    const float4 xpr = masked(raw_chunk((uint32_t)p));
+
+    float4 kv[REG_KEPT / 2];
+#pragma unroll
+    for (int q = 0; q < REG_KEPT / 2; ++q) kv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t sid = NONE;  // lane t: the t-th kept point
+    int ns = 0;
+    for (int it = 0; it < a.iters; ++it) {
+        const double alpha = a.iters > 1 ? a.alpha + it * a.alpha_step : a.alpha;
+        const float al = (float)alpha;
+        const float cterm = (al + 1.0f) * ta;
+        ns = 0;
+        // candidates in blocks of REG_AHEAD: the next block's loads are issued
+        // when a block starts and have the whole block's work to arrive
+        float4 cur[REG_AHEAD], nxt[REG_AHEAD];
+#pragma unroll
+        for (int k = 0; k < REG_AHEAD; ++k) cur[k] = fetch(k);
+        bool go = len > 0;
+        for (int jb = 0; go; jb += REG_AHEAD) {
+#pragma unroll
+            for (int k = 0; k < REG_AHEAD; ++k) nxt[k] = fetch(jb + REG_AHEAD + k);
+#pragma unroll
+            for (int k = 0; k < REG_AHEAD; ++k) {
+                const int j = jb + k;
+                if (!go || j >= len || ns >= a.R) {
+                    go = false;
+                    break;
+                }
+                const uint32_t u = cand_at(j);
+                const float lhs = lhs_at(j);
+                const float4 ur = masked(cur[k]);
+                bool pruned = false;
+                if (ns > 0) {
+                    const int nh = (ns + 1) >> 1;  // kept slots in use per lane group
+                    float sum;
+                    int span;
+                    if (nh <= 2) {
+                        sum = reg_sums<2>(ur, kv, gl);
+                        span = 16;
+                    } else if (nh <= 4) {
+                        sum = reg_sums<4>(ur, kv, gl);
+                        span = 8;
+                    } else if (nh <= 8) {
+                        sum = reg_sums<8>(ur, kv, gl);
+                        span = 4;
+                    } else {
+                        sum = reg_sums<16>(ur, kv, gl);
+                        span = 2;
+                    }
+                    const int t = 2 * (gl / span) + g;  // this lane's kept point
+                    bool dec = false, tie = false;
+                    if (gl % span == 0 && t < ns) {
+                        const float dist = __builtin_sqrtf(sum);
+                        const float ab = al * dist;
+                        const float rhs = ab + cterm;
+                        tie = __builtin_fabsf(lhs - rhs) <= 1e-6f * lhs;
+                        dec = !tie && lhs > rhs;
+                    }
+                    pruned = ballot(dec) != 0;
+                    uint64_t tm = pruned ? 0ull : ballot(tie);
+                    // near-ties: float64 distances from the registers (the
+                    // order of dist_f64_group), one pair at a time
+                    while (tm && !pruned) {
+                        const int l = __builtin_ctzll(tm);
+                        tm &= tm - 1;
+                        const int tt = 2 * ((l & 31) / span) + (l >> 5);
+                        const double a64 = __builtin_sqrt(group_sum_f64<32>(chunk_fma_f64(xpr, ur, 0.0)));
+                        double b2 = 0.0;
+#pragma unroll
+                        for (int q = 0; q < REG_KEPT / 2; ++q)
+                            if (q == (tt >> 1)) b2 = chunk_fma_f64(ur, kv[q], 0.0);  // uniform
+                        b2 = group_sum_f64<32>(b2);  // group tt & 1 holds the pair
+                        b2 = __shfl(b2, (tt & 1) * 32, 64);
+                        const double b64 = __builtin_sqrt(b2);
+                        // every lane holds the same values: the ballot makes
+                        // the decision visibly uniform
+                        pruned = ballot(a64 > alpha * b64 + (alpha + 1.0) * a.tau) != 0;
+                    }
+                }
+                if (!pruned) {
+                    const int q0 = ns >> 1;
+                    const bool mine = g == (ns & 1);
+#pragma unroll
+                    for (int q = 0; q < REG_KEPT / 2; ++q) {
+                        if (q == q0) {  // uniform
+                            kv[q].x = mine ? ur.x : kv[q].x;
+                            kv[q].y = mine ? ur.y : kv[q].y;
+                            kv[q].z = mine ? ur.z : kv[q].z;
+                            kv[q].w = mine ? ur.w : kv[q].w;
+                        }
+                    }
+                    if (lane == ns) sid = u;
+                    ++ns;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < REG_AHEAD; ++k) cur[k] = nxt[k];
+        }
+        if (2 * ns >= a.R) break;
+    }
+    uint32_t *out = a.adj + (size_t)p * a.W;
+    for (int s2 = lane; s2 < a.W; s2 += 64) out[s2] = s2 < ns ? sid : NONE;
+}
+
 using PruneFn = void (*)(PruneArgs);
 
 template <int G, int RND, bool VEC>
@@ -390,6 +573,12 @@ hipError_t launch_prune(const float *points, int64_t n, int d, const uint32_t *c
     PruneArgs a{points, n, d, cand, candD, C, R, W, alpha, tau, adj, copy_upto, iters,
                 alpha_step};
     const bool vec = (d % 4 == 0) && ((uintptr_t)points % 16 == 0);
+    if (vec && d <= 128 && R <= REG_KEPT && C <= REG_CAND) {
+        const int wpb = 4;
+        hipLaunchKernelGGL(prune_reg_kernel<true>, dim3((unsigned)((n + wpb - 1) / wpb)), dim3(64 * wpb),
+                           0, stream, a);
+        return hipGetLastError();
+    }
     const size_t lds_wave = adaptive_lds_per_wave(R, C);
     if (iters > 1 && iters <= MAX_PASSES && lds_wave <= 64 * 1024) {
         // as many waves per workgroup (up to 4) as 64 KB of LDS holds
