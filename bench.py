@@ -507,7 +507,7 @@ def serving_form(cng, torch, x, q, xd, g, gt_ids, a):
                       int(rng.choice([32, 64, 128, 256]))) for _ in arrivals]
             qsel = [rng.integers(0, len(q), nq_) for nq_, _, _ in specs]
             lat, done_q, hits, tot10 = [], 0, 0, 0
-            hitsL, totL = {}, {}
+            hitsL, totL, latL = {}, {}, {}
             backlog, outstanding = [], []   # (arrival, idx)
             i = 0
             t0 = time.perf_counter()
@@ -532,6 +532,7 @@ def serving_form(cng, torch, x, q, xd, g, gt_ids, a):
                         continue
                     t = time.perf_counter() - t0
                     lat.append(t - arrivals[j])
+                    latL.setdefault(specs[j][2], []).append(t - arrivals[j])
                     done_q += specs[j][0]
                     if specs[j][1] == 10:
                         Lj = specs[j][2]
@@ -546,13 +547,25 @@ def serving_form(cng, torch, x, q, xd, g, gt_ids, a):
                     break
             wall = time.perf_counter() - t0
         lat_ms = np.array(lat) * 1e3
+        recL = {L_: hitsL[L_] / totL[L_] for L_ in totL}
+        # the requests whose beam width reaches recall@10 0.95 (k = 10 requests
+        # judge each width; every request of that width counts for latency)
+        okL = sorted(L_ for L_ in recL if recL[L_] >= 0.95)
+        lat95 = np.array([v for L_ in okL for v in latL.get(L_, [])]) * 1e3
         res["runs"].append({"offered_qps": target, "requests": len(lat), "queries": done_q,
                             "achieved_qps": round(done_q / wall, 1),
                             "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
                             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
                             "recall@10_k10_requests": round(hits / max(tot10, 1), 4),
-                            "recall@10_k10_by_L": {str(L_): round(hitsL[L_] / totL[L_], 4)
-                                                   for L_ in sorted(totL)}})
+                            "recall@10_k10_by_L": {str(L_): round(recL[L_], 4) for L_ in sorted(recL)},
+                            "latency_ms_by_L": {str(L_): {"requests": len(v),
+                                                          "p50": round(float(np.percentile(np.array(v) * 1e3, 50)), 3),
+                                                          "p99": round(float(np.percentile(np.array(v) * 1e3, 99)), 3)}
+                                                for L_, v in sorted(latL.items())},
+                            "at_recall_0.95": None if not len(lat95) else {
+                                "L": okL, "requests": int(len(lat95)),
+                                "p50_ms": round(float(np.percentile(lat95, 50)), 3),
+                                "p99_ms": round(float(np.percentile(lat95, 99)), 3)}})
     return res
 
 

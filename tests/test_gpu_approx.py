@@ -16,8 +16,12 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("case", [(1, 3000, 16, 0), (1, 3000, 16, 1), (1, 3000, 16, 8),
-                                  (2, 2000, 32, 6), (3, 700, 8, 4), (4, 2000, 64, 5)])
+                                  (2, 2000, 32, 6), (3, 700, 8, 4), (4, 2000, 64, 5),
+                                  (2, 6000, 64, 2)])
 def test_nndescent_vs_oracle(case):
+    """Case (2, 6000, 64, 2) offers up to 4096 candidates per point in a round,
+    more than the 2048-slot visited table holds: forgotten ids come again and
+    must not enter the list twice."""
     cfg, n, K, rounds = case
     print(f"nndescent cfg{cfg} n={n} K={K} rounds={rounds}", flush=True)
     x, _ = workloads.generate(cfg, n=n, nq=1)
