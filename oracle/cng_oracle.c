@@ -827,8 +827,11 @@ static int search_scored(const orc_scorer *sc, const float *rpts, int64_t n, int
 /* from the traversal tree of s so that every point is reachable.  Reading,    */
 /* in rounds on a fixed snapshot of the graph:                                 */
 /*   Reach <- points reachable from s.  If Reach = P: done.                    */
-/*   U <- P \ Reach.  A <- points of U with no in-edge from U (in id order);   */
-/*   if A is empty, A <- {min U}.                                              */
+/*   U <- P \ Reach.  On the subgraph that U induces, take the strongly        */
+/*   connected components that no edge from the rest of U enters (the source   */
+/*   components: every point of U is reachable from one of them), and let A   */
+/*   be the smallest id of each, in id order.  (A point of U without an       */
+/*   in-edge from U is a source component of its own.)                        */
 /*   For every p in A: run beam-search(G, x_p, s, Lc, Lc) on the snapshot and */
 /*   let t_p be the first point of its result (by (D, id)) whose row has a     */
 /*   free slot; if none has one, the reached point with a free slot nearest to */
@@ -845,6 +848,85 @@ static int row_degree(const uint32_t *adj, int R, uint32_t t)
     int g = 0;
     while (g < R && adj[(size_t)t * R + g] != ORC_NONE) ++g;
     return g;
+}
+
+/* A of a connectivity round: the smallest id of every source component of the
+ * subgraph induced by the unreached points (Tarjan's algorithm, 1972, run
+ * iteratively).  Work arrays of n entries: idx, low, comp (int64), stk, cs
+ * (uint32), cpos (int), flag (bytes: on the stack / component not a source /
+ * component taken).  Returns |A|. */
+static int64_t source_components(const uint32_t *adj, int64_t n, int R, const unsigned char *reached,
+                                 uint32_t *A, int64_t *idx, int64_t *low, int64_t *comp,
+                                 uint32_t *stk, uint32_t *cs, int *cpos, unsigned char *flag)
+{
+    const unsigned char ONSTACK = 1, NOTSRC = 2, TAKEN = 4;
+    for (int64_t v = 0; v < n; ++v) { idx[v] = -1; flag[v] = 0; comp[v] = -1; }
+    int64_t counter = 0, ncomp = 0, sp = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        if (reached[r] || idx[r] >= 0) continue;
+        /* depth-first search from r over unreached points; cs holds the path,
+         * cpos the next edge of each point on it */
+        int64_t csp = 0;
+        cs[csp] = (uint32_t)r; cpos[csp] = 0; ++csp;
+        idx[r] = low[r] = counter++;
+        stk[sp++] = (uint32_t)r; flag[r] |= ONSTACK;
+        while (csp > 0) {
+            const uint32_t u = cs[csp - 1];
+            int j = cpos[csp - 1];
+            int descended = 0;
+            while (j < R) {
+                const uint32_t v = adj[(size_t)u * R + j];
+                if (v == ORC_NONE || (int64_t)v >= n) { j = R; break; }
+                ++j;
+                if (reached[v]) continue;
+                if (idx[v] < 0) {
+                    cpos[csp - 1] = j;
+                    idx[v] = low[v] = counter++;
+                    stk[sp++] = v; flag[v] |= ONSTACK;
+                    cs[csp] = v; cpos[csp] = 0; ++csp;
+                    descended = 1;
+                    break;
+                }
+                if (flag[v] & ONSTACK) low[u] = low[u] < idx[v] ? low[u] : idx[v];
+            }
+            if (descended) continue;
+            /* u is done: close its component if it is a root, then return */
+            if (low[u] == idx[u]) {
+                uint32_t w;
+                do {
+                    w = stk[--sp];
+                    flag[w] &= (unsigned char)~ONSTACK;
+                    comp[w] = ncomp;
+                } while (w != u);
+                ++ncomp;
+            }
+            --csp;
+            if (csp > 0) {
+                const uint32_t parent = cs[csp - 1];
+                low[parent] = low[parent] < low[u] ? low[parent] : low[u];
+            }
+        }
+    }
+    /* components entered by an edge from another component of U; flags of
+     * components are kept at the index of the component */
+    for (int64_t v = 0; v < n; ++v) flag[v] = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        if (reached[u]) continue;
+        for (int j = 0; j < R; ++j) {
+            const uint32_t v = adj[(size_t)u * R + j];
+            if (v == ORC_NONE || (int64_t)v >= n) break;
+            if (!reached[v] && comp[v] != comp[u]) flag[comp[v]] |= NOTSRC;
+        }
+    }
+    int64_t nA = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        if (reached[v]) continue;
+        const int64_t c = comp[v];
+        if (flag[c] & (NOTSRC | TAKEN)) continue;
+        flag[c] |= TAKEN;
+        A[nA++] = (uint32_t)v;
+    }
+    return nA;
 }
 
 static void bfs_mark(const uint32_t *adj, int64_t n, int R, unsigned char *reached, uint32_t *stack,
@@ -870,31 +952,28 @@ int orc_connect(const float *pts, int64_t n, int d, uint32_t *adj, int R, uint32
     if (n < 1 || d < 1 || R < 1 || Lc < 1 || (int64_t)entry >= n) return ORC_EINVAL;
     unsigned char *reached = (unsigned char *)calloc((size_t)n, 1);
     uint32_t *stack = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
-    uint32_t *indeg = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
     uint32_t *A = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
     uint32_t *T = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
     int *deg = (int *)malloc(sizeof(int) * (size_t)n);
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *low = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *comp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    uint32_t *cs = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    int *cpos = (int *)malloc(sizeof(int) * (size_t)n);
+    unsigned char *flag = (unsigned char *)malloc((size_t)n);
     int rc = ORC_OK;
     int64_t added = 0, rounds = 0;
-    if (!reached || !stack || !indeg || !A || !T || !deg) { rc = ORC_ENOMEM; goto done; }
+    if (!reached || !stack || !A || !T || !deg || !idx || !low || !comp || !cs || !cpos || !flag) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
     bfs_mark(adj, n, R, reached, stack, entry);
     for (;;) {
-        int64_t nA = 0, minU = -1;
-        for (int64_t p = 0; p < n; ++p) indeg[p] = 0;
-        for (int64_t w = 0; w < n; ++w) {
-            if (reached[w]) continue;
-            if (minU < 0) minU = w;
-            for (int j = 0; j < R; ++j) {
-                uint32_t v = adj[(size_t)w * R + j];
-                if (v == ORC_NONE || (int64_t)v >= n) break;
-                if (!reached[v]) indeg[v]++;
-            }
-        }
-        if (minU < 0) break; /* everything reachable */
+        int64_t any = 0;
+        for (int64_t w = 0; w < n && !any; ++w) any = !reached[w];
+        if (!any) break; /* everything reachable */
         ++rounds;
-        for (int64_t p = 0; p < n; ++p)
-            if (!reached[p] && indeg[p] == 0) A[nA++] = (uint32_t)p;
-        if (nA == 0) A[nA++] = (uint32_t)minU;
+        const int64_t nA = source_components(adj, n, R, reached, A, idx, low, comp, stack, cs, cpos, flag);
         for (int64_t t = 0; t < n; ++t) deg[t] = row_degree(adj, R, (uint32_t)t);
         int fail = 0;
 #pragma omp parallel
@@ -943,7 +1022,8 @@ int orc_connect(const float *pts, int64_t n, int d, uint32_t *adj, int R, uint32
 done:
     if (n_added) *n_added = added;
     if (n_rounds) *n_rounds = rounds;
-    free(reached); free(stack); free(indeg); free(A); free(T); free(deg);
+    free(reached); free(stack); free(A); free(T); free(deg);
+    free(idx); free(low); free(comp); free(cs); free(cpos); free(flag);
     return rc;
 }
 

@@ -256,10 +256,11 @@ def test_threads_do_not_change_results():
 @pytest.mark.parametrize("mode", [oracle.FP32, oracle.FP64])
 def test_connect_hand_traced_cases(mode):
     """Hand-traced rounds of the connectivity phase (Alg. 3 phase 4): which
-    unreached points are attached in a round (those without an in-edge from
-    the unreached set, else the smallest id), to which row (the first search
-    result with a free slot, else the nearest reached point with one), and in
-    what order competing points are applied."""
+    unreached points are attached in a round (the smallest id of every strongly
+    connected component of the unreached subgraph that no other unreached
+    point enters), to which row (the first search result with a free slot,
+    else the nearest reached point with one), and in what order competing
+    points are applied."""
     g = json.load(open(os.path.join(GOLD, "connect_cases.json")))
     for c in g["cases"]:
         adj, added, rounds = oracle.connect(np.array(c["points"], np.float32),
