@@ -3,8 +3,10 @@
 // misses, as NSG does; the reading implemented here works in rounds on a
 // snapshot of the graph so that the searches of one round run as one batch:
 //   U = points not reachable from the entry (breadth-first search on the GPU);
-//   A = points of U with no in-edge from U, in id order (the smallest id of U
-//       if there is none);
+//   A = the smallest id of every strongly connected component of the
+//       subgraph U induces that no edge from another component of U enters
+//       (its source components: every point of U is reachable from one), in
+//       id order; found on the host (Tarjan's algorithm on U's rows);
 //   every p in A is searched from the entry with beam Lc (the batched beam
 //   search kernel, query = point p) and gets the first result, by (D, id),
 //   whose row has a free slot in the snapshot; if none has one, the reachable
@@ -14,6 +16,9 @@
 //   waits for the next round).
 // Rows have spare slots beyond the pruning cap for exactly these edges.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -29,12 +34,11 @@ constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Counters {
     uint32_t next;      // BFS next-frontier size
-    uint32_t nA;        // |A|
-    uint32_t minU;      // smallest unreached id
+    uint32_t nA;        // |U| (then |A|)
     uint32_t nfb;       // points that need the nearest-free fallback
     uint32_t attached;  // points attached this round
     uint32_t cap_err;   // 1 if some point found no row with room
-    uint32_t pad[2];
+    uint32_t pad[3];
     unsigned long long fb_key;  // (D, id) of the nearest free point
 };
 
@@ -74,13 +78,10 @@ __global__ void bfs_expand(const uint32_t *__restrict__ adj, int W, int64_t n,
 
 __global__ void reset_next(Counters *c) { c->next = 0; }
 
-__global__ void round_init(Counters *c, uint32_t *indeg, int64_t n)
+__global__ void round_init(Counters *c)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) indeg[i] = 0;
-    if (i == 0) {
+    {
         c->nA = 0;
-        c->minU = NONE;
         c->nfb = 0;
         c->attached = 0;
         c->cap_err = 0;
@@ -88,28 +89,10 @@ __global__ void round_init(Counters *c, uint32_t *indeg, int64_t n)
     }
 }
 
-__global__ void indeg_from_unreached(const uint32_t *__restrict__ adj, int W, int64_t n,
-                                     const uint32_t *__restrict__ reached, uint32_t *indeg,
-                                     Counters *c)
-{
-    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= n || reached[w]) return;
-    atomicMin(&c->minU, (uint32_t)w);
-    const uint32_t *row = adj + (size_t)w * W;
-    for (int g = 0; g < W; ++g) {
-        uint32_t v = row[g];
-        if (v == NONE || (int64_t)v >= n) break;
-        if (!reached[v]) atomicAdd(&indeg[v], 1u);
-    }
-}
+// Points of U (listed in id order by count_A / scan_segments / scatter_A).
+__device__ __forceinline__ bool in_A(const uint32_t *reached, int64_t p) { return !reached[p]; }
 
-__device__ __forceinline__ bool in_A(const uint32_t *reached, const uint32_t *indeg, int64_t p)
-{
-    return !reached[p] && indeg[p] == 0;
-}
-
-__global__ __launch_bounds__(256) void count_A(const uint32_t *__restrict__ reached,
-                                               const uint32_t *__restrict__ indeg, int64_t n,
+__global__ __launch_bounds__(256) void count_A(const uint32_t *__restrict__ reached, int64_t n,
                                                uint32_t *__restrict__ segcnt)
 {
     __shared__ uint32_t s;
@@ -119,7 +102,7 @@ __global__ __launch_bounds__(256) void count_A(const uint32_t *__restrict__ reac
     uint32_t k = 0;
     for (int j = threadIdx.x; j < SEG; j += 256) {
         int64_t p = base + j;
-        if (p < n && in_A(reached, indeg, p)) ++k;
+        if (p < n && in_A(reached, p)) ++k;
     }
     atomicAdd(&s, k);
     __syncthreads();
@@ -151,8 +134,7 @@ __global__ __launch_bounds__(1024) void scan_segments(uint32_t *segcnt, int64_t 
 }
 
 // Ordered write of A: each block scans its segment (256 threads x 4 points).
-__global__ __launch_bounds__(256) void scatter_A(const uint32_t *__restrict__ reached,
-                                                 const uint32_t *__restrict__ indeg, int64_t n,
+__global__ __launch_bounds__(256) void scatter_A(const uint32_t *__restrict__ reached, int64_t n,
                                                  const uint32_t *__restrict__ segoff,
                                                  uint32_t *__restrict__ A)
 {
@@ -161,7 +143,7 @@ __global__ __launch_bounds__(256) void scatter_A(const uint32_t *__restrict__ re
     uint32_t f[4], k = 0;
     for (int j = 0; j < 4; ++j) {
         int64_t p = base + j;
-        f[j] = (p < n && in_A(reached, indeg, p)) ? 1u : 0u;
+        f[j] = (p < n && in_A(reached, p)) ? 1u : 0u;
         k += f[j];
     }
     buf[threadIdx.x] = k;
@@ -177,16 +159,20 @@ __global__ __launch_bounds__(256) void scatter_A(const uint32_t *__restrict__ re
         if (f[j]) A[o++] = (uint32_t)(base + j);
 }
 
-__global__ void A_from_min(uint32_t *A, Counters *c)
-{
-    A[0] = c->minU;
-    c->nA = 1;
-}
-
 __global__ void degrees(const uint32_t *__restrict__ adj, int W, int64_t n, uint32_t *__restrict__ deg)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) deg[t] = (uint32_t)row_len(adj + (size_t)t * W, W, n);
+}
+
+// Rows of the points U[u0 .. u0 + cnt) into out [cnt x W].
+__global__ void gather_u_rows(const uint32_t *__restrict__ U, int64_t u0, int64_t cnt,
+                              const uint32_t *__restrict__ adj, int W, uint32_t *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt * W) return;
+    const int64_t i = t / W;
+    out[t] = adj[(size_t)U[u0 + i] * W + (t % W)];
 }
 
 // First beam entry whose row has room (snapshot degrees); else queue a fallback.
@@ -283,12 +269,12 @@ NearestFn pick_nf(int d)
 }
 
 struct Ws {
-    uint32_t *reached, *f0, *f1, *indeg, *deg, *A, *T, *fb, *segcnt, *beam, *entry;
+    uint32_t *reached, *f0, *f1, *deg, *A, *T, *fb, *segcnt, *beam, *entry;
     float *beamD;
     Counters *c;
 };
 
-Ws carve(void *ws, int64_t n, int Lc)
+Ws carve(void *ws, int64_t n, int W, int Lc)
 {
     unsigned char *w = (unsigned char *)ws;
     Ws s;
@@ -300,14 +286,14 @@ Ws carve(void *ws, int64_t n, int Lc)
     s.reached = (uint32_t *)take((size_t)n * 4);
     s.f0 = (uint32_t *)take((size_t)n * 4);
     s.f1 = (uint32_t *)take((size_t)n * 4);
-    s.indeg = (uint32_t *)take((size_t)n * 4);
     s.deg = (uint32_t *)take((size_t)n * 4);
     s.A = (uint32_t *)take((size_t)n * 4);
     s.T = (uint32_t *)take((size_t)n * 4);
     s.fb = (uint32_t *)take((size_t)n * 4);
     s.segcnt = (uint32_t *)take((size_t)((n + SEG - 1) / SEG + 1) * 4);
     int64_t b = n < BATCH ? n : BATCH;
-    s.beam = (uint32_t *)take((size_t)b * Lc * 4);
+    // the beams of a search batch, and the rows of a chunk of U
+    s.beam = (uint32_t *)take((size_t)b * (Lc > W ? Lc : W) * 4);
     s.beamD = (float *)take((size_t)b * Lc * 4);
     s.entry = (uint32_t *)take(4);
     s.c = (Counters *)take(sizeof(Counters));
@@ -344,21 +330,99 @@ hipError_t bfs(const uint32_t *adj, int W, int64_t n, Ws &s, uint32_t *frontier,
     return hipSuccess;
 }
 
+// A of a round, on the host: U (ascending) with its rows (rows[i * W ..] is
+// the row of U[i]).  Tarjan's strongly connected components (1972), with an
+// explicit stack of (point, next edge); a component is a source when no edge
+// from another component of U enters it; A = the smallest id of each source
+// component, ascending.
+std::vector<uint32_t> source_component_mins(const std::vector<uint32_t> &U,
+                                            const std::vector<uint32_t> &rows, int W, int64_t n)
+{
+    const size_t m = U.size();
+    // the subgraph on U as compressed rows of local indices
+    std::vector<size_t> first(m + 1, 0);
+    std::vector<uint32_t> to;
+    to.reserve(m * 2);
+    for (size_t i = 0; i < m; ++i) {
+        for (int g = 0; g < W; ++g) {
+            const uint32_t v = rows[i * (size_t)W + g];
+            if (v == NONE || (int64_t)v >= n) break;
+            const auto it = std::lower_bound(U.begin(), U.end(), v);
+            if (it != U.end() && *it == v) to.push_back((uint32_t)(it - U.begin()));
+        }
+        first[i + 1] = to.size();
+    }
+    std::vector<int64_t> order(m, -1), low(m, 0);
+    std::vector<int64_t> comp(m, -1);
+    std::vector<char> open(m, 0);
+    std::vector<uint32_t> pending;                       // points of unfinished components
+    std::vector<std::pair<uint32_t, size_t>> path;       // (point, next edge)
+    int64_t clock = 0, ncomp = 0;
+    for (size_t r = 0; r < m; ++r) {
+        if (order[r] >= 0) continue;
+        order[r] = low[r] = clock++;
+        pending.push_back((uint32_t)r);
+        open[r] = 1;
+        path.emplace_back((uint32_t)r, first[r]);
+        while (!path.empty()) {
+            const uint32_t u = path.back().first;
+            const size_t e = path.back().second;
+            if (e < first[u + 1]) {
+                path.back().second = e + 1;
+                const uint32_t v = to[e];
+                if (order[v] < 0) {
+                    order[v] = low[v] = clock++;
+                    pending.push_back(v);
+                    open[v] = 1;
+                    path.emplace_back(v, first[v]);
+                } else if (open[v]) {
+                    low[u] = std::min(low[u], order[v]);
+                }
+                continue;
+            }
+            if (low[u] == order[u]) {  // u roots a component
+                uint32_t w;
+                do {
+                    w = pending.back();
+                    pending.pop_back();
+                    open[w] = 0;
+                    comp[w] = ncomp;
+                } while (w != u);
+                ++ncomp;
+            }
+            path.pop_back();
+            if (!path.empty()) low[path.back().first] = std::min(low[path.back().first], low[u]);
+        }
+    }
+    std::vector<char> entered((size_t)ncomp, 0), taken((size_t)ncomp, 0);
+    for (size_t u = 0; u < m; ++u)
+        for (size_t e = first[u]; e < first[u + 1]; ++e)
+            if (comp[to[e]] != comp[u]) entered[(size_t)comp[to[e]]] = 1;
+    std::vector<uint32_t> A;
+    for (size_t i = 0; i < m; ++i) {
+        const size_t c = (size_t)comp[i];
+        if (entered[c] || taken[c]) continue;
+        taken[c] = 1;
+        A.push_back(U[i]);
+    }
+    return A;
+}
+
 }  // namespace
 
 size_t connect_workspace_bytes(int64_t n, int W, int Lc)
 {
-    (void)W;
     int64_t b = n < BATCH ? n : BATCH;
-    return align256((size_t)n * 4) * 8 + align256((size_t)((n + SEG - 1) / SEG + 1) * 4) +
-           align256((size_t)b * Lc * 4) * 2 + align256(4) + align256(sizeof(Counters));
+    return align256((size_t)n * 4) * 7 + align256((size_t)((n + SEG - 1) / SEG + 1) * 4) +
+           align256((size_t)b * (Lc > W ? Lc : W) * 4) + align256((size_t)b * Lc * 4) + align256(4) +
+           align256(sizeof(Counters));
 }
 
 hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int W,
                        uint32_t entry_host, int Lc, int vlog2, void *ws, hipStream_t st,
                        int64_t *rounds, int64_t *added, int *capacity_error)
 {
-    Ws s = carve(ws, n, Lc);
+    Ws s = carve(ws, n, W, Lc);
     *rounds = 0;
     *added = 0;
     *capacity_error = 0;
@@ -379,23 +443,32 @@ hipError_t run_connect(const float *points, int64_t n, int d, uint32_t *adj, int
     hipLaunchKernelGGL(degrees, dim3(gb), dim3(256), 0, st, adj, W, n, s.deg);
     while (reached < n) {
         ++*rounds;
-        hipLaunchKernelGGL(round_init, dim3(gb), dim3(256), 0, st, s.c, s.indeg, n);
-        hipLaunchKernelGGL(indeg_from_unreached, dim3(gb), dim3(256), 0, st, adj, W, n, s.reached,
-                           s.indeg, s.c);
-        hipLaunchKernelGGL(count_A, dim3((unsigned)nseg), dim3(256), 0, st, s.reached, s.indeg, n,
-                           s.segcnt);
+        hipLaunchKernelGGL(round_init, dim3(1), dim3(1), 0, st, s.c);
+        // U in id order into s.A, |U| into c->nA
+        hipLaunchKernelGGL(count_A, dim3((unsigned)nseg), dim3(256), 0, st, s.reached, n, s.segcnt);
         hipLaunchKernelGGL(scan_segments, dim3(1), dim3(1024), 0, st, s.segcnt, nseg, s.c);
-        hipLaunchKernelGGL(scatter_A, dim3((unsigned)nseg), dim3(256), 0, st, s.reached, s.indeg, n,
-                           s.segcnt, s.A);
+        hipLaunchKernelGGL(scatter_A, dim3((unsigned)nseg), dim3(256), 0, st, s.reached, n, s.segcnt, s.A);
         e = read_counters(&h, s.c, st);
         if (e != hipSuccess) return e;
-        if (h.minU == NONE) break;  // the device sees every point reached
+        if (h.nA == 0) break;  // the device sees every point reached
         if (*rounds > n) return hipErrorUnknown;  // each round attaches a point: cannot happen
-        if (h.nA == 0) {
-            hipLaunchKernelGGL(A_from_min, dim3(1), dim3(1), 0, st, s.A, s.c);
-            h.nA = 1;
+        // U and its rows to the host (rows in chunks through the beam buffer)
+        std::vector<uint32_t> Uh(h.nA), rows((size_t)h.nA * W);
+        e = hipMemcpyAsync(Uh.data(), s.A, (size_t)h.nA * 4, hipMemcpyDeviceToHost, st);
+        for (int64_t u0 = 0; e == hipSuccess && u0 < (int64_t)h.nA; u0 += BATCH) {
+            const int64_t cnt = (int64_t)h.nA - u0 < BATCH ? (int64_t)h.nA - u0 : BATCH;
+            hipLaunchKernelGGL(gather_u_rows, dim3((unsigned)((cnt * W + 255) / 256)), dim3(256), 0, st, s.A,
+                               u0, cnt, adj, W, s.beam);
+            e = hipMemcpyAsync(rows.data() + (size_t)u0 * W, s.beam, (size_t)cnt * W * 4,
+                               hipMemcpyDeviceToHost, st);
         }
-        const uint32_t nA = h.nA;
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        const std::vector<uint32_t> Ah = source_component_mins(Uh, rows, W, n);
+        e = hipMemcpyAsync(s.A, Ah.data(), Ah.size() * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        const uint32_t nA = (uint32_t)Ah.size();
         for (int64_t off = 0; off < nA; off += BATCH) {
             const int64_t cnt = nA - off < BATCH ? nA - off : BATCH;
             SearchArgs sa{};
