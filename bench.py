@@ -318,7 +318,7 @@ def main():
             forms["sift_like_10m"] = scale_form(
                 cng, torch, a, 5,
                 {"exact": {}, "graph_candidates_backward": dict(
-                    graph_candidates=True, knn_K=64, knn_rounds=12, backward=True)},
+                    graph_candidates=True, knn_K=48, knn_rounds=12, backward=True)},
                 dtypes=(("bf16", cng.BF16), ("fp8", cng.FP8)), serve=not a.no_serving)
             # the precision workload (1M x 960)
             forms["gist_like_1m"] = scale_form(cng, torch, a, 3, {"exact": {}},
