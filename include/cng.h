@@ -59,7 +59,10 @@ typedef enum {
 typedef struct {
     int32_t R;           /* out-degree cap of pruning (Algorithm 2 keeps at most R), >= 1 */
     int32_t extra;       /* spare slots per row for connectivity edges; row width W = R + extra */
-    int32_t C;           /* candidate-list size (the local-neighbour set V), clamped to n - 1 */
+    int32_t C;           /* candidate-list size (the local-neighbour set V), clamped to n - 1;
+                            up to 896 with the automatic band (larger with an explicit band of
+                            up to 2048 entries; C above the band sends rows to the exhaustive
+                            recomputation) */
     double alpha;        /* alpha of Eq. (1), > 0 */
     double tau;          /* tau of Eq. (1), >= 0 */
     uint32_t flags;      /* CNG_BUILD_* */
@@ -124,7 +127,8 @@ cng_status cng_entry_point(const float *points, int64_t n, int32_t d, uint32_t *
  * columns of `cols` [nc x d] nearest by (D, id), ascending; with exclude_self
  * (requires rows == cols, nr == nc) column r is skipped for row r.  Missing
  * entries (C > available columns) are CNG_NONE / +inf.  band: per-row capacity
- * of the filter (0 = automatic, as in cng_build_params); pass_rows: rows per
+ * of the filter (0 = automatic, as in cng_build_params: then C <= 896, else
+ * CNG_EUNSUPPORTED); pass_rows: rows per
  * filter pass (0 = automatic), results do not depend on it.
  *   ids [nr x C] uint32, D [nr x C] float32 squared distances (fixed order).
  * Replaces the approximate K-NN graph + beam-search candidates of Algorithm 3

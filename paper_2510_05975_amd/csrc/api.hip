@@ -105,9 +105,10 @@ cng_status build_sizes(int64_t n, int32_t d, const cng_build_params *p, BuildSiz
     if (p->visited_log2 != 0 && (p->visited_log2 < 6 || p->visited_log2 > 14))
         return fail(CNG_EINVAL, "visited_log2=%d must be 0 or in [6, 14]", p->visited_log2);
     z->Ceff = (int64_t)p->C > n - 1 ? (int)(n - 1) : p->C;
-    if (2 * z->Ceff + 128 > 512 && p->band == 0) {
-        if (z->Ceff > 192) return fail(CNG_EUNSUPPORTED, "C=%d exceeds 192", p->C);
-    }
+    // the automatic band (2C plus a column tile, to a power of two) must fit the
+    // largest band the kernels take, 2048 entries
+    if (p->band == 0 && 2 * z->Ceff + 256 > 2048)
+        return fail(CNG_EUNSUPPORTED, "C=%d exceeds 896 (pass a band of up to 2048)", p->C);
     z->W = p->R + p->extra;
     z->Lc = p->Lc > 0 ? p->Lc : z->Ceff;
     if (z->Lc > MAX_LEFF) return fail(CNG_EUNSUPPORTED, "Lc=%d exceeds %d", z->Lc, MAX_LEFF);
@@ -355,7 +356,7 @@ cng_status cng_knn_workspace_size(int64_t nr, int64_t nc, int32_t d, int32_t C, 
     if (band < 0 || band > 2048) return fail(CNG_EUNSUPPORTED, "band must be in [0, 2048]");
     if (pass_rows < 0) return fail(CNG_EINVAL, "pass_rows must be >= 0");
     int Ce = C;
-    if (band == 0 && 2 * Ce + 128 > 512) return fail(CNG_EUNSUPPORTED, "C=%d exceeds 192", C);
+    if (band == 0 && 2 * Ce + 256 > 2048) return fail(CNG_EUNSUPPORTED, "C=%d exceeds 896 (pass a band of up to 2048)", C);
     *bytes = cng::knn_plan(nr, nc, d, Ce, band, pass_rows).bytes;
     return ok();
 }

@@ -37,7 +37,7 @@ def test_build_params_rejected(bad):
     assert cng.lib().cng_last_error().decode() != ""
 
 
-@pytest.mark.parametrize("bad", [dict(R=200, extra=100), dict(band=8192), dict(C=300), dict(Lc=1000),
+@pytest.mark.parametrize("bad", [dict(R=200, extra=100), dict(band=8192), dict(C=900), dict(Lc=1000),
                                  dict(alpha_step=1e-6, alpha_max=2.0)])
 def test_build_params_unsupported(bad):
     nb = C.c_size_t(0)
@@ -85,7 +85,7 @@ def test_other_stages_reject():
     fake = C.c_void_p(0x1000)
     nb = C.c_size_t(0)
     assert L.cng_knn_workspace_size(10, 10, 8, 0, 0, 0, C.byref(nb)) == -1
-    assert L.cng_knn_workspace_size(10, 10, 8, 300, 0, 0, C.byref(nb)) == -4
+    assert L.cng_knn_workspace_size(10, 10, 8, 900, 0, 0, C.byref(nb)) == -4
     assert L.cng_knn_workspace_size(10, 10, 8, 4, 0, -1, C.byref(nb)) == -1
     # smaller passes need less band memory
     big, small = C.c_size_t(0), C.c_size_t(0)

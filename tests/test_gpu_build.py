@@ -296,6 +296,29 @@ def test_knn_largest_band(cfg):
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
 
 
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_knn_large_candidate_pool(cfg):
+    """C = 500 (the paper's candidate-pool size) with the automatic band (2048
+    entries per row): every filter form against the oracle."""
+    x, _ = workloads.generate(cfg, n=2600 if cfg != 3 else 1200, nq=1)
+    ids, D, ovf = gpu_knn(x, x, 500, True)
+    assert ovf == 0
+    oids, oD = oracle.knn(x, x, 500, exclude_self=True)
+    assert (ids == oids).all() and same_f32(D, f32_of(oD))
+
+
+def test_build_large_candidate_pool():
+    """A whole build with C = 500 (pruning and connectivity from 500-entry
+    lists, connectivity beam Lc = C) against the oracle."""
+    x, _ = workloads.generate(2, n=3000, nq=1)
+    g = cng.build(dev(x), 32, 500, 1.2)
+    torch.cuda.synchronize()
+    oadj, oe, oadded = oracle.build(x, 32, 500, 1.2)
+    assert g.entry == oe
+    assert (host_ids(g.adj) == oadj).all()
+    assert g.stats["connect_added"] == oadded
+
+
 def test_knn_same_size_different_arrays():
     """As many queries as points but different arrays: not a self-join (no
     locality order, no self exclusion)."""
