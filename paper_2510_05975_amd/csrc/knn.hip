@@ -796,61 +796,68 @@ void filter_bf16(FilterBf16Args A)
         const bool more = t + 1 < ntiles;
         const int64_t next0 = col0 + BN2 < ntiles * BN2 ? col0 + BN2 : 0;
         if (more) fetch(next0);
-        floatx16 acc[2][2];
+        constexpr int NJ = BN2 / 32;  // column blocks of a tile
+        floatx16 acc[2][NJ];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < NJ; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
         const uint16_t *Bb = Bs + (size_t)buf * NP * BN2 * BSTR + (lane & 31) * BSTR + (lane >> 5) * 8;
         const uint16_t *Bl = Bb + (NP - 1) * BN2 * BSTR;  // lo part (split mode)
         // B fragments one k step ahead of the matrix instructions
-        bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bb);
-        bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bb + 32 * BSTR);
-        bf16x8 l0 = b0, l1 = b1;
-        if constexpr (SPLIT) {
-            l0 = *reinterpret_cast<const bf16x8 *>(Bl);
-            l1 = *reinterpret_cast<const bf16x8 *>(Bl + 32 * BSTR);
+        bf16x8 b[NJ], l[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            b[j] = *reinterpret_cast<const bf16x8 *>(Bb + j * 32 * BSTR);
+            l[j] = b[j];
+            if constexpr (SPLIT) l[j] = *reinterpret_cast<const bf16x8 *>(Bl + j * 32 * BSTR);
         }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            bf16x8 n0 = b0, n1 = b1, m0 = l0, m1 = l1;
-            if (ks + 1 < KS) {
-                n0 = *reinterpret_cast<const bf16x8 *>(Bb + (ks + 1) * 16);
-                n1 = *reinterpret_cast<const bf16x8 *>(Bb + 32 * BSTR + (ks + 1) * 16);
-                if constexpr (SPLIT) {
-                    m0 = *reinterpret_cast<const bf16x8 *>(Bl + (ks + 1) * 16);
-                    m1 = *reinterpret_cast<const bf16x8 *>(Bl + 32 * BSTR + (ks + 1) * 16);
+            bf16x8 nb[NJ], nl[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                nb[j] = b[j];
+                nl[j] = l[j];
+                if (ks + 1 < KS) {
+                    nb[j] = *reinterpret_cast<const bf16x8 *>(Bb + j * 32 * BSTR + (ks + 1) * 16);
+                    if constexpr (SPLIT)
+                        nl[j] = *reinterpret_cast<const bf16x8 *>(Bl + j * 32 * BSTR + (ks + 1) * 16);
                 }
             }
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], b0, acc[0][0], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], b0, acc[1][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], b1, acc[0][1], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][ks], b[j], acc[i][j], 0, 0, 0);
             if constexpr (SPLIT) {
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], l0, acc[0][0], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], l0, acc[1][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0][ks], l1, acc[0][1], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1][ks], l1, acc[1][1], 0, 0, 0);
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0][ks], b0, acc[0][0], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1][ks], b0, acc[1][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0][ks], b1, acc[0][1], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1][ks], b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][ks], l[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i][ks], b[j], acc[i][j], 0, 0, 0);
             }
-            b0 = n0;
-            b1 = n1;
-            l0 = m0;
-            l1 = m1;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                b[j] = nb[j];
+                l[j] = nl[j];
+            }
         }
         // next tile into the other buffer now: its loads were issued a whole
         // matrix phase ago, and waiting for them later would also wait for the
         // band stores of the epilogue
         if (more) stash(buf ^ 1);
-        float nyv[2];
+        float nyv[NJ];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) nyv[j] = nys[buf * BN2 + j * 32 + (lane & 31)];
-        const bool wflag = append_tile<2>(a, acc, nyv, th, nullptr, col0, trig, mypos);
+        for (int j = 0; j < NJ; ++j) nyv[j] = nys[buf * BN2 + j * 32 + (lane & 31)];
+        const bool wflag = append_tile<NJ>(a, acc, nyv, th, nullptr, col0, trig, mypos);
         settle_bands<BN2, false>(a, wflag, !more, cnt, thr, erow, keys, hist, rowstart, mypos, th);
         buf ^= 1;
         col0 = next0;
