@@ -22,8 +22,11 @@ A0, AMAX, STEP = 0.9, 1.6, 0.05
 
 @pytest.mark.parametrize("case", [(1, 4000, 24, 64, 0.0), (2, 3000, 32, 128, 0.0),
                                   (4, 3000, 32, 128, 0.0), (1, 3000, 16, 48, 0.2),
-                                  (3, 1000, 48, 192, 0.0)])
+                                  (3, 1000, 48, 192, 0.0), (2, 3000, 48, 160, 0.0)])
 def test_prune_adaptive(case):
+    """d <= 128 with R <= 32 and C <= 128 runs the register kernel; the last two
+    cases (d = 960; R = 48 and C = 160 at d = 128) the kernel with the LDS pair
+    table."""
     cfg, n, R, C, tau = case
     print(f"adaptive prune cfg{cfg} n={n} R={R} C={C} tau={tau}", flush=True)
     x, _ = workloads.generate(cfg, n=n, nq=1)

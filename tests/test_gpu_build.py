@@ -184,6 +184,19 @@ def test_prune_integer_ties_need_fp64():
         assert (host_ids(adj) == oadj).all()
 
 
+@pytest.mark.parametrize("R,C", [(48, 128), (32, 160)])
+def test_prune_beyond_register_kernel(R, C):
+    """d = 128 with R > 32 or C > 128: the kept vectors no longer fit the
+    register kernel, and the memory-reading kernel takes the rows."""
+    x, _ = workloads.generate(2, n=3000, nq=1)
+    cand, D = oracle.knn(x, x, C, exclude_self=True)
+    for alpha in (1.2, 1.0):
+        oadj = oracle.prune(x, cand, D, R=R, alpha=alpha, width=R + 1)
+        adj = cng.prune(dev(x), dev_ids(cand), dev(f32_of(D)), R, alpha, 0.0, width=R + 1)
+        torch.cuda.synchronize()
+        assert (host_ids(adj) == oadj).all()
+
+
 @pytest.mark.parametrize("d", [1, 5, 64, 129, 960])
 def test_prune_dims(d):
     x, _ = workloads.uniform_cube(500, 1, d, seed=d)
