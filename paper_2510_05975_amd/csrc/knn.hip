@@ -160,6 +160,11 @@ struct FilterArgs {
     // its rows are, and wraps around.
     const uint32_t *cell_ends;
     int ncells;
+    // filter_wide: column tiles t0 .. t1 - 1 in this launch (t1 = 0: all), the
+    // rows' thresholds carried from one launch to the next in thrG [chunk]
+    // (the counts in cnt)
+    int64_t t0, t1;
+    float *thrG;
 };
 
 // First column tile of a workgroup's sweep (see FilterArgs::cell_ends).
@@ -911,16 +916,30 @@ void filter_wide(FilterBf16Args A, int K)
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row0 = a.r0 + (int64_t)blockIdx.x * BM2;
     const int64_t rend = a.r0 + a.chunk < a.nr ? a.r0 + a.chunk : a.nr;
-    for (int li = threadIdx.x; li < BM2; li += 256) {
-        int64_t gi = row0 + li;
-        bool live = gi < rend;
-        thr[li] = live ? __builtin_inff() : -__builtin_inff();
-        erow[li] = live ? a.E[gi] : 0.f;
-        cnt[li] = 0;
-    }
+    const int64_t ntiles = (a.nc + BNW - 1) / BNW;
+    // this launch's tiles; the band state of a later launch's rows comes from
+    // the one before (bands, counts and thresholds in global memory)
+    const int64_t tb = a.t1 > 0 ? a.t0 : 0, te = a.t1 > 0 ? a.t1 : ntiles;
+    const bool final_launch = te == ntiles;
+    // thread li owns row li here and in the band positions below
     const uint32_t rowstart = (uint32_t)(blockIdx.x * BM2 + wave * 64 + lane) * (uint32_t)a.CB;
     const int trig = a.CB - BNW;
     uint32_t mypos = rowstart;
+    {
+        const int li = threadIdx.x;
+        const int64_t gi = row0 + li;
+        const bool live = gi < rend;
+        int c = 0;
+        float t = live ? __builtin_inff() : -__builtin_inff();
+        if (live && tb > 0) {
+            c = a.cnt[gi - a.r0];
+            t = a.thrG[gi - a.r0];
+        }
+        thr[li] = t;
+        erow[li] = live ? a.E[gi] : 0.f;
+        cnt[li] = c;
+        mypos = c < 0 ? OVERFLOWED : rowstart + (uint32_t)c;
+    }
 
     // The bf16 copies are k-blocked, [K / KC][rows][KC]: stage k0 of row g
     // starts at k0 * rows + g * KC.  Element offsets of this lane's row
@@ -995,17 +1014,16 @@ void filter_wide(FilterBf16Args A, int K)
     };
 
     const int S = K / KC;  // even
-    const int64_t ntiles = (a.nc + BNW - 1) / BNW;
-    int64_t col0 = first_tile(a, row0, BM2, BNW) * BNW;
+    int64_t col0 = tb * BNW;
     fetch_a(a0, 0);
     fetch_b(col0, 0);
     stash(0);
     __syncthreads();
     float th[2][16];
     load_thr(th, thr);
-    for (int64_t t = 0; t < ntiles; ++t) {
-        const bool more_tiles = t + 1 < ntiles;
-        const int64_t next0 = col0 + BNW < ntiles * BNW ? col0 + BNW : 0;
+    for (int64_t t = tb; t < te; ++t) {
+        const bool more_tiles = t + 1 < te;
+        const int64_t next0 = col0 + BNW;
         float nyv[NJ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
@@ -1040,14 +1058,22 @@ void filter_wide(FilterBf16Args A, int K)
             lds_barrier();
         }
         const bool wflag = append_tile<NJ>(a, acc, nyv, th, thr, col0, trig, mypos);
-        settle_bands<BNW, true>(a, wflag, !more_tiles, cnt, thr, erow, keys, hist, rowstart, mypos, th);
+        settle_bands<BNW, true>(a, wflag, !more_tiles && final_launch, cnt, thr, erow, keys, hist,
+                                rowstart, mypos, th);
         col0 = next0;
+    }
+    if (!final_launch) {
+        // counts back into LDS (the settle after the last tile left them in
+        // the register positions), then state to global memory for the next launch
+        cnt[threadIdx.x] = mypos == OVERFLOWED ? -1 : (int)(mypos - rowstart);
+        __syncthreads();
     }
     for (int li = threadIdx.x; li < BM2; li += 256) {
         int64_t gi = row0 + li;
         if (gi < rend) {
             a.cnt[gi - a.r0] = cnt[li];
-            if (cnt[li] < 0) atomicAdd(&a.st->overflow, 1u);
+            a.thrG[gi - a.r0] = thr[li];
+            if (final_launch && cnt[li] < 0) atomicAdd(&a.st->overflow, 1u);
         }
     }
 }
@@ -1058,6 +1084,9 @@ void filter_wide(FilterBf16Args A, int K)
 constexpr int KCW = 32;   // k values per stage
 constexpr int BNW = 256;  // columns per tile
 constexpr int WPEW = 1;   // waves per SIMD
+// column tiles per launch of the wide filter (1M x 960 candidate search: one
+// launch per pass 7.30 s, 16 or 64 tiles per launch 6.99 s, 4 tiles 7.40 s)
+constexpr int64_t WIDE_TILES = 16;
 
 size_t filter_wide_lds_bytes(int CB, bool split)
 {
@@ -1396,7 +1425,7 @@ KnnPlan knn_plan(int64_t nr, int64_t nc, int d, int C, int band, int64_t pass_ro
     chunk = (chunk + BM2 - 1) / BM2 * BM2;  // whole workgroups of either filter
     p.chunk_rows = chunk;
     p.bytes = align256((size_t)nc * 4) + align256((size_t)nr * 4) * 2 + align256(sizeof(PrepOut)) +
-              align256((size_t)chunk * CB * 4) * 2 + align256((size_t)chunk * 4);
+              align256((size_t)chunk * CB * 4) * 2 + align256((size_t)chunk * 4) * 2;
     {  // bf16 copies (hi and lo parts) for the matrix-core filters
         const int K = bf16_row_len(d);
         p.bytes += (align256((size_t)nc * K * 2) + align256((size_t)nr * K * 2)) * 2;
@@ -1435,6 +1464,8 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
     uint32_t *bandI = (uint32_t *)w;
     w += align256((size_t)plan.chunk_rows * CB * 4);
     int *cnt = (int *)w;
+    w += align256((size_t)plan.chunk_rows * 4);
+    float *thrG = (float *)w;  // row thresholds between the wide filter's launches
     w += align256((size_t)plan.chunk_rows * 4);
     const int K16 = bf16_row_len(d);
     uint16_t *cols16 = (uint16_t *)w;
@@ -1557,11 +1588,20 @@ hipError_t launch_knn(const float *rows, int64_t nr, const float *cols, int64_t 
         FilterArgs fa{rows, nr, r0, chunk, cols, nc, d, C, exclude_self, nyf, Ef, CB, bandF, bandI, cnt, st,
                       cell_ends, ordered ? plan.order_K : 0};
         if ((use_bf16 || use_split) && wide) {
-            FilterBf16Args fb{fa, rows16, cols16, rows16lo, cols16lo};
+            // the column sweep in launches of WIDE_TILES column tiles: the
+            // workgroups in flight then work on the same columns, which the
+            // L2 of each XCD serves to all of them
             const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
             const unsigned lds = (unsigned)filter_wide_lds_bytes(CB, use_split);
-            if (use_split) hipLaunchKernelGGL((filter_wide<KCW, BNW, true, WPEW>), dim3(blocks), dim3(256), lds, stream, fb, K16);
-            else hipLaunchKernelGGL((filter_wide<KCW, BNW, false, WPEW>), dim3(blocks), dim3(256), lds, stream, fb, K16);
+            const int64_t ntw = (nc + BNW - 1) / BNW;
+            for (int64_t t0 = 0; t0 < ntw; t0 += WIDE_TILES) {
+                fa.t0 = t0;
+                fa.t1 = t0 + WIDE_TILES < ntw ? t0 + WIDE_TILES : ntw;
+                fa.thrG = thrG;
+                FilterBf16Args fb{fa, rows16, cols16, rows16lo, cols16lo};
+                if (use_split) hipLaunchKernelGGL((filter_wide<KCW, BNW, true, WPEW>), dim3(blocks), dim3(256), lds, stream, fb, K16);
+                else hipLaunchKernelGGL((filter_wide<KCW, BNW, false, WPEW>), dim3(blocks), dim3(256), lds, stream, fb, K16);
+            }
         } else if (use_bf16 || use_split) {
             FilterBf16Args fb{fa, rows16, cols16, rows16lo, cols16lo};
             const unsigned blocks = (unsigned)((chunk + BM2 - 1) / BM2);
