@@ -89,7 +89,32 @@ __device__ __forceinline__ int lower_bound_keys(const uint64_t *arr, int cnt, ui
 // vectors b + t * NG + grp for t < UB; all loads of a batch are issued before
 // any sum (a batch's trip count is uniform across the wavefront), then the UB
 // sums are formed together by group_sums.
-template <int G, int RND, bool VEC, int UB, int ST>
+
+// The raw chunks of a batch (VEC layout); slots that no group fills this
+// batch (b + t * NG >= m, uniform) are zeros.  GUARD: lanes past d load
+// nothing (zeros); without it every chunk lies in the row (d == RND * 4 * G),
+// so no lane is masked off around a load.
+template <bool GUARD, int NG, int RND, int UB, int ST>
+__device__ __forceinline__ void load_batch(typename RawChunk<ST>::type (&raw)[UB][RND],
+                                           const void *__restrict__ vecs, const uint32_t (&ids)[UB], int d,
+                                           int gl, int b, int m)
+{
+#pragma unroll
+    for (int t = 0; t < UB; ++t) {
+        if (b + t * NG < m) {  // uniform: some group still has a vector
+#pragma unroll
+            for (int r = 0; r < RND; ++r) raw[t][r] = load_raw<ST, GUARD>(vecs, ids[t], d, r, gl);
+        } else {
+#pragma unroll
+            for (int r = 0; r < RND; ++r) raw[t][r] = typename RawChunk<ST>::type{};
+        }
+    }
+}
+
+// PADDED: the 64 entries of cid past m repeat cid[0], so a group past the
+// end of the list reads its entry as it is instead of a clamped one (and
+// loads the lines of a vector that another group loads too).
+template <int G, int RND, bool VEC, int UB, int ST, bool PADDED = false>
 __device__ __forceinline__ void gather_dists(const void *__restrict__ vecs, const float *__restrict__ scales,
                                              int d, const uint32_t *cid, int m, const float4 (&qr)[RND],
                                              float *dsc, float qq = 0.f, int part = 0, int parts = 1)
@@ -107,29 +132,49 @@ __device__ __forceinline__ void gather_dists(const void *__restrict__ vecs, cons
         if (ST == 2 && gl % SPAN == 0 && cw < m) sn = sn2[cid[cw]];
         // Loads only: nothing in a guarded block uses a loaded value, so no
         // wait separates the loads of a batch.  A group past the end of the
-        // list re-reads vector b and its sum is never written.
+        // list re-reads vector b (PADDED: vector 0) and its sum is never
+        // written.
         float acc[UB];
         if (VEC) {
-            typename RawChunk<ST>::type raw[UB][RND];
+            // the batch's ids first (LDS reads, one wait for all of them)
+            uint32_t ids[UB];
 #pragma unroll
             for (int t = 0; t < UB; ++t) {
-                if (b + t * NG < m) {  // uniform: some group still has a vector
-                    const int c = b + t * NG + grp;
-                    const uint32_t id = cid[c < m ? c : b];
-#pragma unroll
-                    for (int r = 0; r < RND; ++r) raw[t][r] = load_raw<ST>(vecs, id, d, r, gl);
-                } else {
-#pragma unroll
-                    for (int r = 0; r < RND; ++r) raw[t][r] = typename RawChunk<ST>::type{};
-                }
+                const int c = b + t * NG + grp;
+                ids[t] = cid[PADDED || c < m ? c : b];
             }
+            typename RawChunk<ST>::type raw[UB][RND];
+            if constexpr (PADDED) {
+                // every slot loads (its id is valid) and every lane loads
+                // (lanes past d from the row's start); a lane past d keeps
+                // its partial sum unchanged in that round, as a zero chunk
+                // would leave it
 #pragma unroll
-            for (int t = 0; t < UB; ++t) {
-                acc[t] = 0.f;
+                for (int t = 0; t < UB; ++t)
 #pragma unroll
-                for (int r = 0; r < RND; ++r) {
-                    if (ST == 2) acc[t] = chunk_dot(decode_chunk(raw[t][r]), qr[r], acc[t]);
-                    else acc[t] = chunk_fma(decode_chunk(raw[t][r]), qr[r], acc[t]);
+                    for (int r = 0; r < RND; ++r)
+                        raw[t][r] = load_raw<ST, false>(vecs, ids[t], d, (r * 32 + gl) * 4 < d ? r : 0,
+                                                        (r * 32 + gl) * 4 < d ? gl : 0);
+#pragma unroll
+                for (int t = 0; t < UB; ++t) {
+                    acc[t] = 0.f;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) {
+                        const float nv = ST == 2 ? chunk_dot(decode_chunk(raw[t][r]), qr[r], acc[t])
+                                                 : chunk_fma(decode_chunk(raw[t][r]), qr[r], acc[t]);
+                        acc[t] = (r * 32 + gl) * 4 < d ? nv : acc[t];
+                    }
+                }
+            } else {
+                load_batch<true, NG, RND, UB, ST>(raw, vecs, ids, d, gl, b, m);
+#pragma unroll
+                for (int t = 0; t < UB; ++t) {
+                    acc[t] = 0.f;
+#pragma unroll
+                    for (int r = 0; r < RND; ++r) {
+                        if (ST == 2) acc[t] = chunk_dot(decode_chunk(raw[t][r]), qr[r], acc[t]);
+                        else acc[t] = chunk_fma(decode_chunk(raw[t][r]), qr[r], acc[t]);
+                    }
                 }
             }
         } else {
@@ -301,6 +346,9 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
                 int slot = __popcll(fm & ((1ull << lane) - 1ull));
                 s.cid[slot] = v;
             }
+            // entries past the list repeat its first id (gather_dists, PADDED)
+            if (m > 0 && lane >= m)
+                s.cid[lane] = (uint32_t)__builtin_amdgcn_readlane((int)v, __ffsll((unsigned long long)fm) - 1);
             wave_sync();
             // ---- distances: G lanes per vector, NG vectors per instruction
             if constexpr (COOP > 1) {
@@ -309,7 +357,7 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
                 gather_dists<G, RND, VEC, UB, ST>(a.vecs, a.scales, d, s.cid, m, qr, s.dsc, qq, 0, COOP);
                 __syncthreads();  // every share of the distances is in dsc
             } else {
-                gather_dists<G, RND, VEC, UB, ST>(a.vecs, a.scales, d, s.cid, m, qr, s.dsc, qq);
+                gather_dists<G, RND, VEC, UB, ST, true>(a.vecs, a.scales, d, s.cid, m, qr, s.dsc, qq);
             }
             wave_sync();
             ndc += (uint32_t)m;
@@ -324,9 +372,9 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
         // ---- re-rank the converged beam with the float32 vectors
         for (int b0 = 0; b0 < qn; b0 += 64) {
             const int cnt = qn - b0 < 64 ? qn - b0 : 64;
-            if (lane < cnt) s.cid[lane] = key_id(qa[b0 + lane]);
+            s.cid[lane] = key_id(qa[b0 + (lane < cnt ? lane : 0)]);
             wave_sync();
-            gather_dists<G, RND, VEC, UB, 0>(a.points, nullptr, d, s.cid, cnt, qr, s.dsc);
+            gather_dists<G, RND, VEC, UB, 0, true>(a.points, nullptr, d, s.cid, cnt, qr, s.dsc);
             wave_sync();
             if (lane < cnt) qa[b0 + lane] = make_key(s.dsc[lane], key_id(qa[b0 + lane]));
             wave_sync();

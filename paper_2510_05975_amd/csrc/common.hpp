@@ -60,7 +60,9 @@ __device__ __forceinline__ double group_sum_f64(double v)
 }
 
 // Lane exchange v[lane ^ OFF] within aligned groups of 32 lanes: DPP quad
-// permutations for offsets 1 and 2, ds_swizzle (xor mode) above.
+// permutations for offsets 1 and 2, a DPP rotation of the 16-lane row by 8
+// (lane i of a row takes lane (i + 8) mod 16 = i ^ 8) for offset 8,
+// ds_swizzle (xor mode) for 4 and 16.
 template <int OFF>
 __device__ __forceinline__ float xor_lane(float v)
 {
@@ -68,8 +70,19 @@ __device__ __forceinline__ float xor_lane(float v)
     int r;
     if (OFF == 1) r = __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);       // quad_perm [1,0,3,2]
     else if (OFF == 2) r = __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    else if (OFF == 8) r = __builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false); // row_ror:8
     else r = __builtin_amdgcn_ds_swizzle(x, 0x1F | (OFF << 10));                      // and 0x1F, xor OFF
     return __int_as_float(r);
+}
+
+// a[l] + a[l ^ 16] for the lanes of even 16-lane rows and b[l] + b[l ^ 16] for
+// those of odd rows, with one gfx950 row swap: it exchanges the odd rows of a
+// with the even rows of b, after which the two registers hold, lane by lane,
+// exactly the two addends (in some order; the sum is the same).
+__device__ __forceinline__ float swap16_sum(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // Fixed-order sums of UB vectors at once.  v[t] holds this lane's partial sum
@@ -83,7 +96,17 @@ __device__ __forceinline__ float xor_lane(float v)
 template <int G, int UB, int OFF, int N>
 __device__ __forceinline__ void halve_step(float (&v)[UB], int gl)
 {
-    if constexpr (OFF >= 1) {
+    if constexpr (OFF == 16) {
+        // lanes below 16 of a group keep vector j, the others vector j + N/2
+        if constexpr (N > 1) {
+#pragma unroll
+            for (int j = 0; j < N / 2; ++j) v[j] = swap16_sum(v[j], v[j + N / 2]);
+            halve_step<G, UB, 8, N / 2>(v, gl);
+        } else {
+            v[0] = swap16_sum(v[0], v[0]);
+            halve_step<G, UB, 8, 1>(v, gl);
+        }
+    } else if constexpr (OFF >= 1) {
         if constexpr (N > 1) {
             const bool hi = (gl & OFF) != 0;
 #pragma unroll
@@ -222,9 +245,9 @@ __device__ __forceinline__ float4 load_stored(const void *__restrict__ base, siz
     const int i = (r * 32 + gl) * 4;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (ST == 0) {
-        return load_chunk<VEC>(reinterpret_cast<const float *>(base) + row * d, d, r, gl);
+        return load_chunk<VEC>(reinterpret_cast<const float *>(base) + row * (uint32_t)d, d, r, gl);
     } else if (ST == 1) {
-        const uint16_t *p = reinterpret_cast<const uint16_t *>(base) + row * d + i;
+        const uint16_t *p = reinterpret_cast<const uint16_t *>(base) + row * (uint32_t)d + i;
         if (VEC) {
             if (i < d) {
                 const uint2 w = *reinterpret_cast<const uint2 *>(p);
@@ -239,7 +262,7 @@ __device__ __forceinline__ float4 load_stored(const void *__restrict__ base, siz
         }
         return v;
     } else {
-        const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + row * d + i;
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + row * (uint32_t)d + i;
         if (VEC) {
             if (i < d) {
                 const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
@@ -264,16 +287,16 @@ template <> struct RawChunk<0> { typedef float4 type; };
 template <> struct RawChunk<1> { typedef uint2 type; };
 template <> struct RawChunk<2> { typedef uint32_t type; };
 
-template <int ST>
+template <int ST, bool GUARD = true>
 __device__ __forceinline__ typename RawChunk<ST>::type load_raw(const void *__restrict__ base, size_t row,
                                                                 int d, int r, int gl)
 {
     typedef typename RawChunk<ST>::type T;
     const int i = (r * 32 + gl) * 4;
-    if (i >= d) return T{};
-    if (ST == 0) return *reinterpret_cast<const T *>(reinterpret_cast<const float *>(base) + row * d + i);
-    if (ST == 1) return *reinterpret_cast<const T *>(reinterpret_cast<const uint16_t *>(base) + row * d + i);
-    return *reinterpret_cast<const T *>(reinterpret_cast<const uint8_t *>(base) + row * d + i);
+    if (GUARD && i >= d) return T{};  // without GUARD the caller knows every chunk is in the row
+    if (ST == 0) return *reinterpret_cast<const T *>(reinterpret_cast<const float *>(base) + row * (uint32_t)d + i);
+    if (ST == 1) return *reinterpret_cast<const T *>(reinterpret_cast<const uint16_t *>(base) + row * (uint32_t)d + i);
+    return *reinterpret_cast<const T *>(reinterpret_cast<const uint8_t *>(base) + row * (uint32_t)d + i);
 }
 
 __device__ __forceinline__ float4 decode_chunk(float4 w) { return w; }
