@@ -23,6 +23,9 @@
  *     in D are broken by the smaller id.  Returned distances are sqrt(D).
  *   - An adjacency is n rows of W uint32 ids.  A row's out-neighbours are the
  *     entries before its first CNG_NONE (or first id >= n); the rest is padding.
+ *     A row lists an id at most once (the builders' rows do): a search marks
+ *     a row's ids visited together, and an id repeated within one row may be
+ *     taken twice once its visited table is full, leaving a damaged beam.
  *   - Arguments are validated before any launch.  On a non-OK status nothing
  *     was launched (EINVAL/EUNSUPPORTED) or outputs are undefined (EDEVICE);
  *     cng_last_error() gives a message.  No C++ exception crosses the ABI.

@@ -35,6 +35,11 @@ namespace beam {
 
 constexpr int PROBES = 8;
 
+// Marks id visited; false if it was.  The lanes of one call must hold distinct
+// ids: when every probed slot holds another id, the home slot is overwritten
+// (the old id is forgotten and may be scored again, which merge_keys
+// tolerates), and three lanes meeting there, two of them with the same id,
+// would each be told their id is new.
 __device__ __forceinline__ bool visit(uint32_t *vis, int vlog2, uint32_t id)
 {
     const uint32_t mask = (1u << vlog2) - 1u;
