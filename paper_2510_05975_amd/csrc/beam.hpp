@@ -379,7 +379,14 @@ __device__ void beam_query(const SearchArgs a, int64_t qi, WaveLds s)
             const int cnt = qn - b0 < 64 ? qn - b0 : 64;
             s.cid[lane] = key_id(qa[b0 + (lane < cnt ? lane : 0)]);
             wave_sync();
-            gather_dists<G, RND, VEC, UB, 0, true>(a.points, nullptr, d, s.cid, cnt, qr, s.dsc);
+            // float32 rows take 2 (bf16) or 4 (fp8) times the registers of
+            // stored ones: a batch of as many registers, but at least two
+            // vectors per group (measured, 1M x 128 at L = 80: bf16 0.996 ->
+            // 0.972 ms, fp8 0.938 -> 0.921 ms; 1M x 960 at L = 352, bf16 with
+            // one vector per group instead of two 4.74 -> 5.79 ms)
+            constexpr int UBS = ST == 1 ? UB / 2 : UB / 4;
+            constexpr int UBR = UB < 2 ? 1 : UBS > 2 ? UBS : 2;
+            gather_dists<G, RND, VEC, UBR, 0, true>(a.points, nullptr, d, s.cid, cnt, qr, s.dsc);
             wave_sync();
             if (lane < cnt) qa[b0 + lane] = make_key(s.dsc[lane], key_id(qa[b0 + lane]));
             wave_sync();

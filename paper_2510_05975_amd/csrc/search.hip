@@ -72,10 +72,22 @@ __global__ __launch_bounds__(64 * COOPW) void search_coop_kernel(SearchArgs a)
 
 using KernelFn = void (*)(SearchArgs);
 
+// Vectors per lane group in one load batch for 32-lane groups: the batch's raw
+// words (UB x RND chunks of W words: 4 for float32, 1 for fp8) kept within
+// BUDGET registers, at most 16.  bf16 batches are sized as float32 ones
+// (measured, 1M x 960 with 1000 queries at L = 352: twice the bf16 batch,
+// 4.7 -> 8.8 ms per launch; fp8 with the full budget 5.25 -> 5.05 ms).
+template <int RND, int ST, int BUDGET>
+constexpr int batch_ub()
+{
+    constexpr int w = RND * (ST == 2 ? 1 : 4);
+    return w >= BUDGET ? 1 : BUDGET / w > 16 ? 16 : BUDGET / w;
+}
+
 template <int G, int RND, bool VEC, int ST, int UBX = 0>
 KernelFn pick_qs(int qs)
 {
-    constexpr int UB = UBX ? UBX : G == 32 ? (RND >= 16 ? 1 : 16 / RND) : G / 2;
+    constexpr int UB = UBX ? UBX : G == 32 ? batch_ub<RND, ST, 64>() : G / 2;
     switch (qs) {
     case 1: return search_kernel<G, RND, VEC, 1, UB, ST>;
     case 2: return search_kernel<G, RND, VEC, 2, UB, ST>;
@@ -84,21 +96,20 @@ KernelFn pick_qs(int qs)
     }
 }
 
-// deep: a launch of few queries leaves the GPU mostly idle, so float32
-// searches with 257 <= d <= 1024 take twice the vectors per load batch (more
-// registers, half the memory round trips per hop).
+// deep: a launch of few queries leaves the GPU mostly idle, so float32 and
+// fp8 searches with 257 <= d <= 1024 give a load batch twice the registers
+// (more vectors per batch, half the memory round trips per hop).
 template <bool VEC, int ST>
 KernelFn pick_kernel(int d, int qs, bool deep)
 {
+    constexpr int DEEP_REGS = ST == 1 ? 64 : 128;
     if (d <= 32) return pick_qs<8, 1, VEC, ST>(qs);
     if (d <= 64) return pick_qs<16, 1, VEC, ST>(qs);
     int rnd = (d + 127) / 128;
     if (rnd <= 1) return pick_qs<32, 1, VEC, ST>(qs);
     if (rnd <= 2) return pick_qs<32, 2, VEC, ST>(qs);
-    if constexpr (ST == 0) {
-        if (deep && rnd > 2 && rnd <= 4) return pick_qs<32, 4, VEC, ST, 8>(qs);
-        if (deep && rnd > 4 && rnd <= 8) return pick_qs<32, 8, VEC, ST, 4>(qs);
-    }
+    if (deep && rnd > 2 && rnd <= 4) return pick_qs<32, 4, VEC, ST, batch_ub<4, ST, DEEP_REGS>()>(qs);
+    if (deep && rnd > 4 && rnd <= 8) return pick_qs<32, 8, VEC, ST, batch_ub<8, ST, DEEP_REGS>()>(qs);
     if (rnd <= 4) return pick_qs<32, 4, VEC, ST>(qs);
     if (rnd <= 8) return pick_qs<32, 8, VEC, ST>(qs);
     if (rnd <= 16) return pick_qs<32, 16, VEC, ST>(qs);
