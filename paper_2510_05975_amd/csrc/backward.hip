@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void gather_candidates(GatherArgs a)
     const int64_t s0 = a.off[p];
     const int64_t total = nown + (a.off[p + 1] - s0);
 
-    const float *xp = a.points + (size_t)p * d;
+    const float *xp = a.points + (size_t)p * (uint32_t)d;
     float4 xr[RND];
 #pragma unroll
     for (int r = 0; r < RND; ++r) xr[r] = load_chunk<VEC>(xp, d, r, gl);
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void gather_candidates(GatherArgs a)
         }
         float4 yr[RND];
         if (valid) {
-            const float *y = a.points + (size_t)id * d;
+            const float *y = a.points + (size_t)id * (uint32_t)d;
 #pragma unroll
             for (int r = 0; r < RND; ++r) yr[r] = load_chunk<VEC>(y, d, r, gl);
         } else {

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void nearest_free(const float *__restrict__ pt
     const int lane = lane_id(), grp = lane / G, gl = lane % G;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const float *xp = pts + (size_t)p * d;
+    const float *xp = pts + (size_t)p * (uint32_t)d;
     float4 xr[RND];
 #pragma unroll
     for (int r = 0; r < RND; ++r) xr[r] = load_chunk<VEC>(xp, d, r, gl);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void nearest_free(const float *__restrict__ pt
         const bool cand = w < n && reached[w] && deg[w] < (uint32_t)W;
         float acc = 0.f;
         if (cand) {
-            const float *y = pts + (size_t)w * d;
+            const float *y = pts + (size_t)w * (uint32_t)d;
 #pragma unroll
             for (int r = 0; r < RND; ++r) acc = chunk_fma(xr[r], load_chunk<VEC>(y, d, r, gl), acc);
         }

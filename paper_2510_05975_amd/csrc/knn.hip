@@ -1126,7 +1126,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a)
     if (c < 0) return;  // exhaustive path
     const int64_t gi = a.order ? (int64_t)a.order[gp] : gp;
     uint64_t *buf = reinterpret_cast<uint64_t *>(smem) + (size_t)wave * a.CB;
-    const float *x = a.rows + (size_t)gi * a.d;
+    const float *x = a.rows + (size_t)gi * (uint32_t)a.d;
     float4 xr[RND];
 #pragma unroll
     for (int r = 0; r < RND; ++r) xr[r] = load_chunk<VEC>(x, a.d, r, gl);
@@ -1142,7 +1142,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a)
             id = a.order ? a.order[bI[e]] : bI[e];
             is_self = id == self;
             if (is_self) id = 0;  // its key is replaced below
-            const float *y = a.cols + (size_t)id * a.d;
+            const float *y = a.cols + (size_t)id * (uint32_t)a.d;
 #pragma unroll
             for (int r = 0; r < RND; ++r) yr[r] = load_chunk<VEC>(y, a.d, r, gl);
         } else {
@@ -1192,7 +1192,7 @@ __global__ __launch_bounds__(256) void exhaustive_kernel(RerankArgs a, int exclu
     const int64_t gi = a.order ? (int64_t)a.order[gp] : gp;
     // CBX (a power of two) >= C + 64: room for one more batch after a cut to C
     uint64_t *buf = reinterpret_cast<uint64_t *>(smem) + (size_t)wave * CBX;
-    const float *x = a.rows + (size_t)gi * a.d;
+    const float *x = a.rows + (size_t)gi * (uint32_t)a.d;
     float4 xr[RND];
 #pragma unroll
     for (int r = 0; r < RND; ++r) xr[r] = load_chunk<VEC>(x, a.d, r, gl);
@@ -1203,7 +1203,7 @@ __global__ __launch_bounds__(256) void exhaustive_kernel(RerankArgs a, int exclu
         float4 yr[RND];
         const bool in = col < a.nc && !(exclude_self && col == gi);
         if (in) {
-            const float *y = a.cols + (size_t)col * a.d;
+            const float *y = a.cols + (size_t)col * (uint32_t)a.d;
 #pragma unroll
             for (int r = 0; r < RND; ++r) yr[r] = load_chunk<VEC>(y, a.d, r, gl);
         } else {

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void nnd_kernel(NndArgs a)
     uint32_t *vis = old + 64;
     const int d = a.d, K = a.K;
     const int gl = lane % G;
-    const float *xp = a.points + (size_t)p * d;
+    const float *xp = a.points + (size_t)p * (uint32_t)d;
     float4 qr[RND];
 #pragma unroll
     for (int r = 0; r < RND; ++r) qr[r] = load_chunk<VEC>(xp, d, r, gl);

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
 
     if (copy_short_list(a, p)) return;
     const float ta = (float)a.tau;
-    const float *xp = a.points + (size_t)p * d;
+    const float *xp = a.points + (size_t)p * (uint32_t)d;
 
     int ns = 0;
     for (int it = 0; it < a.iters; ++it) {
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
         const uint32_t u = a.cand[(size_t)p * a.C + j];
         if (u == NONE || (int64_t)u >= a.n) break;
         const float lhs = __builtin_sqrtf(a.candD[(size_t)p * a.C + j]);
-        const float *xu = a.points + (size_t)u * d;
+        const float *xu = a.points + (size_t)u * (uint32_t)d;
         float4 ur[RND];
 #pragma unroll
         for (int r = 0; r < RND; ++r) ur[r] = load_chunk<VEC>(xu, d, r, gl);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
     }
     wave_sync();
     const float ta = (float)a.tau;
-    const float *xp = a.points + (size_t)p * d;
+    const float *xp = a.points + (size_t)p * (uint32_t)d;
 
     int ns = 0;
     for (int it = 0; it < a.iters; ++it) {
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
             if (u == NONE || (int64_t)u >= a.n) break;
             const float lhs = lhsv[j];
             const float band = 1e-6f * lhs;
-            const float *xu = a.points + (size_t)u * d;
+            const float *xu = a.points + (size_t)u * (uint32_t)d;
             bool have_u = false;
             float4 ur[RND];
             bool pruned = false;
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(256) void prune_reg_kernel(PruneArgs a)
     // divergent branch, so a use waits for its own loads only.
     const bool in_d = gl * 4 < d;
     auto raw_chunk = [&](uint32_t id) -> float4 {
-        return *reinterpret_cast<const float4 *>(a.points + (size_t)id * d + (in_d ? gl * 4 : 0));
+        return *reinterpret_cast<const float4 *>(a.points + (size_t)id * (uint32_t)d + (in_d ? gl * 4 : 0));
     };
     auto masked = [&](float4 v) -> float4 { return in_d ? v : make_float4(0.f, 0.f, 0.f, 0.f); };
     // candidate j's chunk; past the list, point p's own (a valid row)
