@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
             for (int t = 0; t < UB; ++t) {
                 int c = b + t * NG + grp;
                 if (c < ns) {
-                    const float *xv = a.points + (size_t)S[c] * d;
+                    const float *xv = a.points + (size_t)S[c] * (uint32_t)d;
 #pragma unroll
                     for (int r = 0; r < RND; ++r) vr[t][r] = load_chunk<VEC>(xv, d, r, gl);
                 } else {
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
                     const float band = 1e-6f * lhs;
                     bool dec;
                     if (diff <= band) {  // near-tie: re-decide in float64 (same for the whole group)
-                        const float *xv = a.points + (size_t)S[c] * d;
+                        const float *xv = a.points + (size_t)S[c] * (uint32_t)d;
                         double a64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xp, xu, d, gl));
                         double b64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xu, xv, d, gl));
                         double ab64 = alpha * b64;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void prune_adaptive_kernel(PruneArgs a)
                     const int l = __builtin_ctzll(tm);
                     tm &= tm - 1;
                     const uint32_t v = Sid[b + l];
-                    const float *xv = a.points + (size_t)v * d;
+                    const float *xv = a.points + (size_t)v * (uint32_t)d;
                     const double a64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xp, xu, d, gl));
                     const double b64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xu, xv, d, gl));
                     pruned = a64 > alpha * b64 + (alpha + 1.0) * a.tau;
