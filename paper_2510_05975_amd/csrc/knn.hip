@@ -593,11 +593,24 @@ __device__ __forceinline__ void append_block(const FilterArgs &a, const floatx16
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
+        // The 16 elements of a lane first decide together whether any of them
+        // is at or below its threshold: the least F - t of the lane (exact in
+        // sign; a NaN F, past the last column, drops out of the minimum), one
+        // ballot and one branch for the block instead of one per element.
+        float Fv[16], tv[16];
+        float g = __builtin_inff();
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const float F = __builtin_fmaf(-2.0f, acc[i][J][r], ny[J]);
-            const float t = thr_lds ? thr_lds[wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)]
-                                    : th[i][r];
+            Fv[r] = __builtin_fmaf(-2.0f, acc[i][J][r], ny[J]);
+            tv[r] = thr_lds ? thr_lds[wave * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)]
+                            : th[i][r];
+            g = __builtin_fminf(g, Fv[r] - tv[r]);
+        }
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(g <= 0.0f) == 0, 1)) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float F = Fv[r];
+            const float t = tv[r];
             const uint64_t m = __builtin_amdgcn_ballot_w64(F <= t);
             if (__builtin_expect(m != 0, 0)) {
 #pragma unroll
