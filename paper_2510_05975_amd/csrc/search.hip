@@ -76,7 +76,8 @@ using KernelFn = void (*)(SearchArgs);
 // words (UB x RND chunks of W words: 4 for float32, 1 for fp8) kept within
 // BUDGET registers, at most 16.  bf16 batches are sized as float32 ones
 // (measured, 1M x 960 with 1000 queries at L = 352: twice the bf16 batch,
-// 4.7 -> 8.8 ms per launch; fp8 with the full budget 5.25 -> 5.05 ms).
+// 4.7 -> 8.8 ms per launch; fp8 batches of 8 vectors instead of 2, 5.25 ->
+// 3.50 ms, of 16 vectors 5.05 ms).
 template <int RND, int ST, int BUDGET>
 constexpr int batch_ub()
 {
@@ -96,13 +97,13 @@ KernelFn pick_qs(int qs)
     }
 }
 
-// deep: a launch of few queries leaves the GPU mostly idle, so float32 and
-// fp8 searches with 257 <= d <= 1024 give a load batch twice the registers
-// (more vectors per batch, half the memory round trips per hop).
+// deep: a launch of few queries leaves the GPU mostly idle, so float32
+// searches with 257 <= d <= 1024 give a load batch twice the registers (more
+// vectors per batch, half the memory round trips per hop).
 template <bool VEC, int ST>
 KernelFn pick_kernel(int d, int qs, bool deep)
 {
-    constexpr int DEEP_REGS = ST == 1 ? 64 : 128;
+    constexpr int DEEP_REGS = ST == 0 ? 128 : 64;
     if (d <= 32) return pick_qs<8, 1, VEC, ST>(qs);
     if (d <= 64) return pick_qs<16, 1, VEC, ST>(qs);
     int rnd = (d + 127) / 128;
