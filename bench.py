@@ -42,7 +42,7 @@ BF16_MFMA_TFLOPS = 2500.0
 # (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain
 # elementwise kernel of known size gives), in bytes per launch, keyed by workload
 # and beam width.  Valid only while the search kernel's sources hash to `src`.
-SEARCH_TRAFFIC = {("sift_like_1m", 80): dict(bytes=10.269e9, src="1d733d7a3138a4f3")}
+SEARCH_TRAFFIC = {("sift_like_1m", 80): dict(bytes=10.269e9, src="9779b713ca639eef")}
 KERNEL_SOURCES = ("paper_2510_05975_amd/csrc/search.hip", "paper_2510_05975_amd/csrc/beam.hpp",
                   "paper_2510_05975_amd/csrc/common.hpp")
 
