@@ -13,8 +13,10 @@
 // Three kernels make the same decisions: prune_reg_kernel (d <= 128, R <= 32,
 // C <= 128: kept vectors in registers; 1M x 128, R = 32: 11 ms against 33 ms
 // for prune_kernel, adaptive alpha 0.9 .. 1.6: 92 ms against 192 ms for the
-// table kernel), prune_kernel (fixed alpha otherwise) and
-// prune_adaptive_kernel (adaptive alpha otherwise).
+// table kernel), prune_kernel (fixed alpha otherwise; candidates taken in
+// pairs, so that one read of the kept rows from L2 serves two of them: 1M x
+// 960, R = 48, C = 192: 653 -> 381 ms) and prune_adaptive_kernel (adaptive
+// alpha otherwise).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -98,16 +100,42 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
     const float al = (float)alpha;
     const float cterm = (al + 1.0f) * ta;
     ns = 0;
-    for (int j = 0; j < a.C && ns < a.R; ++j) {
-        const uint32_t u = a.cand[(size_t)p * a.C + j];
-        if (u == NONE || (int64_t)u >= a.n) break;
-        const float lhs = __builtin_sqrtf(a.candD[(size_t)p * a.C + j]);
-        const float *xu = a.points + (size_t)u * (uint32_t)d;
-        float4 ur[RND];
+    // the decision of Eq. (1) for a candidate (lhs = its distance to p, xu its
+    // row) against a kept point (summed squared distance acc, id v): float32
+    // unless near a tie, then float64 (the same for the whole group)
+    auto decide = [&](float lhs, float acc, const float *xu, uint32_t v) -> bool {
+        const float dist = __builtin_sqrtf(acc);
+        const float rhs = al * dist + cterm;
+        if (__builtin_fabsf(lhs - rhs) <= 1e-6f * lhs) {
+            const float *xv = a.points + (size_t)v * (uint32_t)d;
+            const double a64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xp, xu, d, gl));
+            const double b64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xu, xv, d, gl));
+            return a64 > alpha * b64 + (alpha + 1.0) * a.tau;
+        }
+        return lhs > rhs;
+    };
+    // Candidates in pairs: both are compared with each batch of kept points
+    // (one read of the kept rows serves two candidates); the second is then
+    // compared with the first if the first was kept, so each sees exactly the
+    // points kept before it.
+    for (int j = 0; j < a.C && ns < a.R; j += 2) {
+        const uint32_t u0 = a.cand[(size_t)p * a.C + j];
+        if (u0 == NONE || (int64_t)u0 >= a.n) break;
+        const uint32_t c1 = j + 1 < a.C ? a.cand[(size_t)p * a.C + j + 1] : NONE;
+        const bool has1 = c1 != NONE && (int64_t)c1 < a.n;
+        const uint32_t u1 = has1 ? c1 : u0;
+        const float lhs0 = __builtin_sqrtf(a.candD[(size_t)p * a.C + j]);
+        const float lhs1 = has1 ? __builtin_sqrtf(a.candD[(size_t)p * a.C + j + 1]) : 0.f;
+        const float *xu0 = a.points + (size_t)u0 * (uint32_t)d;
+        const float *xu1 = a.points + (size_t)u1 * (uint32_t)d;
+        float4 ur0[RND], ur1[RND];
 #pragma unroll
-        for (int r = 0; r < RND; ++r) ur[r] = load_chunk<VEC>(xu, d, r, gl);
-        bool pruned = false;
-        for (int b = 0; b < ns && !pruned; b += NG * UB) {
+        for (int r = 0; r < RND; ++r) {
+            ur0[r] = load_chunk<VEC>(xu0, d, r, gl);
+            ur1[r] = load_chunk<VEC>(xu1, d, r, gl);
+        }
+        bool pr0 = false, pr1 = !has1;
+        for (int b = 0; b < ns && !(pr0 && pr1); b += NG * UB) {
             float4 vr[UB][RND];
 #pragma unroll
             for (int t = 0; t < UB; ++t) {
@@ -121,39 +149,50 @@ __global__ __launch_bounds__(256) void prune_kernel(PruneArgs a)
                     for (int r = 0; r < RND; ++r) vr[t][r] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
-            bool hit = false;
+            bool hit0 = false, hit1 = false;
 #pragma unroll
             for (int t = 0; t < UB; ++t) {
-                float acc = 0.f;
+                float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
-                for (int r = 0; r < RND; ++r) acc = chunk_fma(ur[r], vr[t][r], acc);
-                acc = group_sum<G>(acc);
+                for (int r = 0; r < RND; ++r) {
+                    acc0 = chunk_fma(ur0[r], vr[t][r], acc0);
+                    acc1 = chunk_fma(ur1[r], vr[t][r], acc1);
+                }
+                acc0 = group_sum<G>(acc0);
+                acc1 = group_sum<G>(acc1);
                 const int c = b + t * NG + grp;
                 if (c < ns) {
-                    const float dist = __builtin_sqrtf(acc);
-                    const float ab = al * dist;
-                    const float rhs = ab + cterm;
-                    const float diff = __builtin_fabsf(lhs - rhs);
-                    const float band = 1e-6f * lhs;
-                    bool dec;
-                    if (diff <= band) {  // near-tie: re-decide in float64 (same for the whole group)
-                        const float *xv = a.points + (size_t)S[c] * (uint32_t)d;
-                        double a64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xp, xu, d, gl));
-                        double b64 = __builtin_sqrt(dist_f64_group<G, RND, VEC>(xu, xv, d, gl));
-                        double ab64 = alpha * b64;
-                        double c64 = (alpha + 1.0) * a.tau;
-                        dec = a64 > ab64 + c64;
-                    } else {
-                        dec = lhs > rhs;
-                    }
-                    hit = hit || (dec && gl == 0);
+                    const uint32_t v = S[c];
+                    if (!pr0) hit0 = hit0 || (decide(lhs0, acc0, xu0, v) && gl == 0);
+                    if (!pr1) hit1 = hit1 || (decide(lhs1, acc1, xu1, v) && gl == 0);
                 }
             }
-            pruned = ballot(hit) != 0;
+            pr0 = pr0 || ballot(hit0) != 0;
+            pr1 = pr1 || ballot(hit1) != 0;
         }
-        if (!pruned) {
+        bool kept0 = false;
+        if (!pr0) {
             wave_sync();
-            if (lane == 0) S[ns] = u;
+            if (lane == 0) S[ns] = u0;
+            wave_sync();
+            ++ns;
+            kept0 = true;
+        }
+        if (!has1 || ns >= a.R) {
+            if (j + 1 < a.C && !has1) break;  // the list ends at j + 1
+            continue;
+        }
+        if (!pr1 && kept0) {
+            // the second against the first, now kept
+            float acc = 0.f;
+#pragma unroll
+            for (int r = 0; r < RND; ++r) acc = chunk_fma(ur1[r], ur0[r], acc);
+            acc = group_sum<G>(acc);
+            pr1 = ballot(decide(lhs1, acc, xu1, u0) && gl == 0) != 0;
+        }
+        if (!pr1) {
+            wave_sync();
+            if (lane == 0) S[ns] = u1;
             wave_sync();
             ++ns;
         }
