@@ -197,7 +197,7 @@ def test_prune_beyond_register_kernel(R, C):
         assert (host_ids(adj) == oadj).all()
 
 
-@pytest.mark.parametrize("d", [1, 5, 64, 129, 960])
+@pytest.mark.parametrize("d", [1, 5, 64, 129, 960, 1500, 3001])
 def test_prune_dims(d):
     x, _ = workloads.uniform_cube(500, 1, d, seed=d)
     cand, D = oracle.knn(x, x, 32, exclude_self=True)
