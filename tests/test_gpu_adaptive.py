@@ -38,6 +38,20 @@ def test_prune_adaptive(case):
     assert (host_ids(got) == want).all()
 
 
+@pytest.mark.parametrize("d", [1500, 3001])
+def test_prune_adaptive_long_rows(d):
+    """Rows of 12 and 24 chunks of 128 values (aligned and not) in the kernel
+    with the LDS pair table."""
+    print(f"adaptive prune d={d}", flush=True)
+    x, _ = workloads.uniform_cube(500, 1, d, seed=d)
+    cand, D = oracle.knn(x, x, 32, exclude_self=True)
+    want = oracle.prune(x, cand, D, 12, A0, width=13, alpha_max=AMAX, alpha_step=STEP)
+    got = cng.prune(dev(x), dev_ids(cand), dev(f32_of(D)), 12, A0, 0.0, width=13, alpha_max=AMAX,
+                    alpha_step=STEP)
+    torch.cuda.synchronize()
+    assert (host_ids(got) == want).all()
+
+
 @pytest.mark.parametrize("step,R", [(0.02, 15), (0.01, 16)])
 def test_prune_adaptive_many_passes(step, R):
     """36 passes (all alpha passes in one sweep) and 71 passes (more than the
