@@ -130,7 +130,7 @@ def test_knn_more_rows_than_columns_wide(d, lo, hi):
     assert (ids == oids).all() and same_f32(D, f32_of(oD))
 
 
-@pytest.mark.parametrize("d", [1, 3, 7, 33, 100, 129, 136, 200, 300])
+@pytest.mark.parametrize("d", [1, 3, 7, 33, 100, 129, 136, 200, 300, 1500, 4096])
 def test_knn_dims(d):
     x, _ = workloads.uniform_cube(700, 1, d, seed=d)
     ids, D, _ = gpu_knn(x, x, 16, True)

@@ -81,7 +81,8 @@ def test_hand_traced_line():
     assert h[0] == len(g["expect_hops"]) and n[0] == g["expect_ndc"]
 
 
-@pytest.mark.parametrize("d", [1, 3, 5, 31, 32, 33, 64, 65, 96, 100, 128, 129, 256, 300, 960])
+@pytest.mark.parametrize("d", [1, 3, 5, 31, 32, 33, 64, 65, 96, 100, 128, 129, 256, 300, 960, 1500,
+                               3001, 4096])
 def test_dimensions(d):
     print(f"search d={d}", flush=True)
     x, q = workloads.uniform_cube(600, 20, d, seed=d)
