@@ -76,8 +76,8 @@ def test_quantized_search_bit_exact(dtype, cfg, n, R, C):
         assert (g[2] == o[2]).all() and (g[3] == o[3]).all()
 
 
-@pytest.mark.parametrize("d", [5, 33, 100])
-def test_quantized_search_odd_dims(d):
+@pytest.mark.parametrize("d", [5, 33, 100, 300, 1500, 4096])
+def test_quantized_search_dims(d):
     x, q = workloads.uniform_cube(800, 30, d, seed=d)
     adj, e, _ = oracle.build(x, 10, 20, 1.2)
     for dtype in (cng.BF16, cng.FP8):
