@@ -248,6 +248,19 @@ def test_build_bit_exact(case):
     assert g.stats["connect_added"] == oadded
 
 
+@pytest.mark.parametrize("d", [2049, 4096])
+def test_build_long_rows(d):
+    """Whole builds at the longest rows the interface accepts (the streamed
+    split filter, pruning over 17-32 chunks of 128 values, connectivity)."""
+    print(f"build d={d}", flush=True)
+    x, _ = workloads.uniform_cube(800, 1, d, seed=d)
+    oadj, oe, oadded = oracle.build(x, 16, 32, 1.2)
+    g = cng.build(dev(x), 16, 32, 1.2)
+    assert g.entry == oe
+    assert (host_ids(g.adj) == oadj).all()
+    assert g.stats["connect_added"] == oadded
+
+
 @pytest.mark.parametrize("d,lo,hi", [(128, 0, 256), (96, 0, 256), (64, 0, 256), (17, 0, 256),
                                      (32, -90, 91), (128, -1, 2)])
 def test_knn_small_integer_bf16_path(d, lo, hi):
